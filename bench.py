@@ -1,0 +1,193 @@
+#!/usr/bin/env python
+"""Benchmark of the Heisenberg Pauli-propagation hot path on one MI355X.
+
+Workload: the 127-qubit heavy-hex kicked Ising circuit (Eq. (u)), observable
+sigma_z^62, theta_h = 0.8, theta_zz = -pi/2, relative truncation eps0 = 1e-4
+after every gate, binary64 coefficients.  One step = one Trotter step: the
+fused RZZ(-pi/2) layer with its re-sort, the 127 RX gates (each one streaming
+merge pass) and the <Z62> readout.  --warmup W Trotter steps run untimed (they
+also build the operator the timed steps start from), then --steps K steps are
+timed: Trotter steps W+1 .. W+K of the circuit.
+
+Metric: Pauli-string updates per second = sum over the 271 gates of every
+timed step of the number of strings the gate acts on, divided by the wall time
+(Results: the paper's per-gate cost is linear in |O|).  The roofline entry is
+for the dominant kernel, the RX merge pass: algorithmic bytes per launch =
+(strings read + strings written) x 40 B, divided by its mean launch time from
+HIP events on the library's stream.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(theta, eps0, budget_s):
+    """The FP64 std::map oracle, single-threaded, on a bounded sample of the
+    same workload: Trotter steps 1.. from the start, gate by gate, until the
+    time budget is spent.  Same metric (string-updates/s)."""
+    import numpy as np
+    import workload as w
+    from oracle import OracleSum, build
+
+    build(force=False)
+    lat = w.eagle_127()
+    terms, coef = w.single_pauli_term(lat.n, {62: "Z"})
+    o = OracleSum(lat.n, terms, coef)
+    zz, rx = w.kicked_ising_step(lat, theta)
+    gates = w.GateList.concat([zz, rx])
+    t0 = time.perf_counter()
+    n_gates = 0
+    steps_done = 0
+    ez = []
+    while time.perf_counter() - t0 < budget_s:
+        for g in range(len(gates)):
+            o.apply(w.GateList(gates.gens[g:g + 1], gates.thetas[g:g + 1]), eps0)
+            n_gates += 1
+            if time.perf_counter() - t0 >= budget_s:
+                break
+        else:
+            steps_done += 1
+            ez.append(float(o.expectation_z()[0]))
+    dt = time.perf_counter() - t0
+    part = n_gates - steps_done * len(gates)
+    return {
+        "value": o.updates() / dt,
+        "unit": "string-updates/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": f"Trotter steps 1-{steps_done} of the same workload plus {part} gates of step "
+                  f"{steps_done + 1} ({n_gates} gates, {dt:.1f} s, {o.updates():.3g} string-updates)",
+    }, ez
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=18)
+    ap.add_argument("--theta", type=float, default=0.8)
+    ap.add_argument("--eps", type=float, default=1e-4)
+    ap.add_argument("--dtype", choices=["f64", "f32"], default="f64")
+    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--verbose", action="store_true")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(each MI355X would hold one shard of the operator; see DESIGN.md).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2506_13241_amd as P
+    import workload as w
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    lat = w.eagle_127()
+    zz, rx = w.kicked_ising_step(lat, args.theta)
+    terms, coef = w.single_pauli_term(lat.n, {62: "Z"})
+    dtype = P.PS_F64 if args.dtype == "f64" else P.PS_F32
+    ps = P.PauliSum(lat.n, terms, coef, dtype=dtype, capacity=1 << 22)
+
+    ez_all = []
+    t_start = time.perf_counter()
+    for s in range(args.warmup):
+        ps.apply_rotation_layer(zz, args.eps).apply_rotation_layer(rx, args.eps)
+        ez_all.append(float(ps.expectation_z()[0]))
+        if args.verbose:
+            log(f"warmup step {s + 1}: |O|={ps.size()} <Z62>={ez_all[-1]:.12f} t={time.perf_counter() - t_start:.2f}s")
+    n_before = ps.size()
+    ps.stats(reset=True)
+    ps.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        ps.apply_rotation_layer(zz, args.eps).apply_rotation_layer(rx, args.eps)
+        ez_all.append(float(ps.expectation_z()[0]))
+        if args.verbose:
+            log(f"timed step {args.warmup + s + 1}: <Z62>={ez_all[-1]:.12f} t={time.perf_counter() - t0:.2f}s")
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    st = ps.stats()
+    ps.set_timing(False)
+    n_after = ps.size()
+
+    updates = st["updates"]
+    bps = st["bytes_per_string"]
+    rx_bytes = (st["rx_in"] + st["rx_out"]) * bps
+    rx_ms_mean = st["rx_ms"] / max(st["rx_launches"], 1)
+    achieved = rx_bytes / (st["rx_ms"] * 1e-3) / 1e9 if st["rx_ms"] > 0 else 0.0
+    roofline = {
+        "bound": "hbm",
+        "kernel": "k_rx_merge",
+        "achieved": round(achieved, 1),
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": round(achieved / HBM_PEAK_GBS, 4),
+        "traffic": None,
+        "launches": int(st["rx_launches"]),
+        "mean_launch_ms": round(rx_ms_mean, 4),
+        "algorithmic_bytes_per_launch": round(rx_bytes / max(st["rx_launches"], 1)),
+    }
+    extra = {
+        "strings_before": n_before,
+        "strings_after": n_after,
+        "ez_z62_per_step": ez_all,
+        "ms_rx_merge_total": round(st["rx_ms"], 3),
+        "ms_clifford_total": round(st["cliff_ms"], 3),
+        "ms_sort_total": round(st["sort_ms"], 3),
+        "sort_passes": int(st["sort_passes"]),
+        "paper_time_per_gate_ms": round(dt / args.steps / 271 * 1e3, 4),
+    }
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu, ez_cpu = cpu_baseline(args.theta, args.eps, args.cpu_budget)
+        k = min(len(ez_cpu), len(ez_all))
+        if k:
+            extra["dz_vs_oracle_max"] = max(abs(a - b) for a, b in zip(ez_all[:k], ez_cpu[:k]))
+            extra["dz_vs_oracle_steps"] = k
+    line = {
+        "metric": "Pauli-string updates/s (and s per Trotter step) at 127q",
+        "value": updates / dt,
+        "unit": "string-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.dtype,
+        "data": "synthetic: deterministic kicked-Ising circuit, no dataset",
+        "config": {
+            "workload": f"kicked Ising 127q heavy-hex, O0=Z62, theta_h={args.theta}, theta_zz=-pi/2, "
+                        f"eps0={args.eps} per gate, Trotter steps {args.warmup + 1}-{args.warmup + args.steps}",
+            "qubits": 127,
+            "gates_per_step": 271,
+        },
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "extra": extra,
+    }
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

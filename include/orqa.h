@@ -1,0 +1,186 @@
+/*
+ * orqa.h -- C ABI of the MI355X (gfx950) Heisenberg Pauli-propagation library.
+ *
+ * The library holds an observable O = sum_I O_I sigma_I (Methods, Eq. define_O)
+ * as a set of Pauli strings with real coefficients in GPU memory and conjugates
+ * it by Pauli rotations exp(-i theta sigma_J / 2) (Appendix A, gate tuple
+ * (J, theta_J)) using the coefficient update of Eq. update_rule, with optional
+ * dynamic truncation |O_I| <= eps0 * max_I |O_I| after every gate
+ * (Eq. truncation1).  <Z> is the sum of the coefficients of strings made of
+ * identities and sigma_z only (Eq. magnetization).
+ *
+ * Pauli strings.  ps_pauli holds the x and z bitmasks of a string on up to 128
+ * qubits; qubit q is bit (q & 63) of word (q >> 6).  Letters: I=(0,0), X=(1,0),
+ * Y=(1,1), Z=(0,1).  The paper's 2-bit code (h,l) maps to this by x = h xor l,
+ * z = h (Methods, Eq. (1)).
+ *
+ * Coefficient lanes.  Each string carries n_lanes coefficients (1..32).  A lane
+ * is an independent operator that shares the key set with the others, with its
+ * own initial coefficients and its own angle per gate; the library applies one
+ * key pass to all lanes.  Coefficients are passed lane-minor: coeffs[t*n_lanes+a].
+ *
+ * Precision.  PS_F64 stores and computes coefficients in binary64.  PS_F32
+ * stores binary32 coefficients; the per-gate cos/sin products and the sum of the
+ * (at most two) contributions to a string are formed in compensated binary32
+ * arithmetic (error-free products and two-sum, one final rounding).  Expectation
+ * values and norms are always accumulated in binary64.
+ *
+ * Streams and memory.  All device work of a handle is enqueued on the HIP stream
+ * given at creation (NULL: the null stream).  Device memory is owned by the
+ * handle and grows on demand.  Calls that return values to the host
+ * synchronise that stream.  A handle must not be used by two threads at once.
+ *
+ * Errors.  Every call returns PS_OK or a negative status; ps_last_error() gives
+ * a message for the calling thread's last failure.  Host arrays passed in are
+ * only read during the call.
+ */
+#ifndef ORQA_H
+#define ORQA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ps_handle ps_handle;
+
+typedef struct {
+    uint64_t x[2];
+    uint64_t z[2];
+} ps_pauli;
+
+enum {
+    PS_OK = 0,
+    PS_ERR_INVALID = -1,     /* bad argument: sizes, null pointers, bits above n_qubits */
+    PS_ERR_CAPACITY = -2,    /* device memory exhausted or above max capacity */
+    PS_ERR_HIP = -3,         /* a HIP runtime call failed */
+    PS_ERR_NONFINITE = -4,   /* NaN/Inf coefficient or angle */
+    PS_ERR_UNSUPPORTED = -5, /* combination not implemented (see message) */
+    PS_ERR_DEVICE = -6       /* a kernel reported an internal failure */
+};
+
+enum { PS_F64 = 0, PS_F32 = 1 };
+enum { PS_TRUNC_NONE = 0, PS_TRUNC_MAGNITUDE = 1, PS_TRUNC_LEARNED = 2 };
+
+/*
+ * pauli_sum_create -- upload an initial operator (Appendix A: the partial
+ * representation O = {(I, O_I)} as a list of tuples).
+ *   n_qubits  1..128.  Every term must be zero above bit n_qubits-1
+ *             (else PS_ERR_INVALID).
+ *   n_lanes   1..32 coefficient lanes.
+ *   dtype     PS_F64 or PS_F32.
+ *   capacity  initial number of strings to reserve (0: library default); the
+ *             handle grows beyond it when a gate needs more.
+ *   terms     n_terms strings (host).  Duplicates are summed.
+ *   coeffs    n_terms*n_lanes binary64 values (host), lane-minor.
+ *   hip_stream  hipStream_t to run on, or NULL.
+ *   out       receives the handle.
+ */
+int pauli_sum_create(int n_qubits, int n_lanes, int dtype, size_t capacity,
+                     const ps_pauli* terms, const double* coeffs, size_t n_terms,
+                     void* hip_stream, ps_handle** out);
+
+/* pauli_sum_destroy -- free all device memory of the handle (NULL is a no-op). */
+int pauli_sum_destroy(ps_handle* h);
+
+/*
+ * apply_rotation_layer -- conjugate the operator by n_gates Pauli rotations in
+ * the order given (Heisenberg order: gate 0 acts on the observable first), each
+ * O <- U^dag O U with U = exp(-i theta sigma_J / 2), coefficient update of
+ * Eq. update_rule (Algorithm 1, gate loop).
+ *   gens     n_gates generators sigma_J (host).
+ *   thetas   n_gates*n_lanes angles (host), lane-minor.  Angles within
+ *            1e-12*max(1,|theta|) of a multiple of pi/2 use exact cos/sin in
+ *            {0,+-1}; a zero factor creates no string.
+ *   rel_eps  eps0 of Eq. truncation1: after every gate drop every string whose
+ *            coefficient satisfies |O_I,a| <= rel_eps * max_I |O_I,a| in every
+ *            lane a (max over the whole operator after that gate).  rel_eps <= 0
+ *            keeps every generated string, exact zeros included.
+ *   trunc_mode  PS_TRUNC_MAGNITUDE (rule above), PS_TRUNC_NONE (rel_eps
+ *            ignored), PS_TRUNC_LEARNED (rule above with |O_I| scaled by the
+ *            loaded scorer's estimate of the string's future weight, see
+ *            pauli_sum_load_scorer).
+ * Fast paths: runs of Clifford gates whose generators hold only Z letters
+ * (e.g. RZZ(-pi/2) layers) are fused into one pass plus one re-sort; sigma_x
+ * rotations on consecutive qubits q, q+1, ... (each layer ascending, starting at
+ * qubit 0) run as one streaming pass per gate.  Any other generator takes the
+ * general branch / sort / reduce path.
+ * On PS_ERR_CAPACITY the gates before the failing one have been applied
+ * (pauli_sum_gates_applied tells how many) and the handle stays usable.
+ */
+int apply_rotation_layer(ps_handle* h, const ps_pauli* gens, const double* thetas,
+                         size_t n_gates, double rel_eps, int trunc_mode);
+
+/* Number of gates of the last apply_rotation_layer call that were applied. */
+int pauli_sum_gates_applied(ps_handle* h, size_t* n);
+
+/*
+ * pauli_sum_truncate -- one truncation of the current operator with the rule
+ * of Eq. truncation1 (Algorithm 1, truncation loop).  Named with the library
+ * prefix so it does not clash with POSIX truncate(2).
+ */
+int pauli_sum_truncate(ps_handle* h, double rel_eps, int trunc_mode);
+
+/* expectation_z -- <0|O|0> per lane (Eq. magnetization), binary64 (host out[n_lanes]). */
+int expectation_z(ps_handle* h, double* out);
+
+/* pauli_sum_size -- number of strings held (|O|, the effective complexity, Methods). */
+int pauli_sum_size(ps_handle* h, size_t* n);
+
+/* pauli_sum_norm2 -- sum_I O_I,a^2 per lane, binary64 (host out[n_lanes]). */
+int pauli_sum_norm2(ps_handle* h, double* out);
+
+/*
+ * pauli_sum_export -- copy up to cap strings to the host, sorted by
+ * (x[1], x[0], z[1], z[0]) ascending.  coeffs receives cap*n_lanes values of
+ * the handle's dtype (double for PS_F64, float for PS_F32), lane-minor.
+ * *n receives the number of strings held; if it exceeds cap nothing is written
+ * and PS_ERR_CAPACITY is returned.
+ */
+int pauli_sum_export(ps_handle* h, ps_pauli* keys, void* coeffs, size_t cap, size_t* n);
+
+/*
+ * pauli_sum_load_scorer -- load the weights of the learned truncation scorer
+ * (an MLP 160->128->128->1 with GELU, bf16 weights, fp32 accumulation) used by
+ * PS_TRUNC_LEARNED.  bf16_w holds W1 (128x160), W2 (128x128), W3 (1x128), row
+ * major, n_w = 37376; f32_b holds b1 (128), b2 (128), b3 (1), n_b = 257.
+ * obs_qubit is the qubit the observable sits on (distance features).
+ */
+int pauli_sum_load_scorer(ps_handle* h, const uint16_t* bf16_w, size_t n_w,
+                          const float* f32_b, size_t n_b, int obs_qubit);
+
+/*
+ * Counters and timing for measurement.  Counters accumulate since creation or
+ * the last reset; kernel times are only collected while timing is enabled
+ * (HIP events around each launch on the handle's stream, read back at the
+ * synchronisation points of apply_rotation_layer).
+ *   updates        sum over gates of the number of strings the gate read
+ *                  (|O| before the gate, the paper's per-gate cost measure)
+ *   gates          gates applied
+ *   rx_launches    streaming RX merge launches; rx_in / rx_out strings read /
+ *                  written by them; rx_ms their summed kernel time
+ *   cliff_launches fused Clifford / compaction launches, cliff_ms their time
+ *   sort_passes    radix-sort passes, sort_ms their time
+ *   bytes_per_string  key + coefficient bytes of one stored string
+ */
+typedef struct {
+    double updates, gates;
+    double rx_launches, rx_in, rx_out, rx_ms;
+    double cliff_launches, cliff_in, cliff_ms;
+    double sort_passes, sort_elems, sort_ms;
+    double bytes_per_string;
+} ps_stats;
+
+int pauli_sum_set_timing(ps_handle* h, int enable);
+int pauli_sum_stats(ps_handle* h, ps_stats* out, int reset);
+
+/* Message for the calling thread's last non-OK status (never NULL). */
+const char* ps_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ORQA_H */

@@ -1,0 +1,233 @@
+"""Thin Python binding of the gfx950 Pauli-propagation library (liborqa_hip.so).
+
+Argument marshalling only: every step of the propagation runs in the HIP
+kernels behind the C ABI declared in include/orqa.h.  PyTorch is used only to
+obtain the current HIP stream.  Importing this package never falls back to
+anything else: if the shared library is missing, every call raises.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liborqa_hip.so")
+
+PS_OK, PS_ERR_INVALID, PS_ERR_CAPACITY, PS_ERR_HIP, PS_ERR_NONFINITE, PS_ERR_UNSUPPORTED, PS_ERR_DEVICE = (
+    0, -1, -2, -3, -4, -5, -6)
+PS_F64, PS_F32 = 0, 1
+PS_TRUNC_NONE, PS_TRUNC_MAGNITUDE, PS_TRUNC_LEARNED = 0, 1, 2
+
+EXPORTED_SYMBOLS = (
+    "pauli_sum_create", "pauli_sum_destroy", "apply_rotation_layer", "pauli_sum_gates_applied",
+    "pauli_sum_truncate", "expectation_z", "pauli_sum_size", "pauli_sum_norm2", "pauli_sum_export",
+    "pauli_sum_load_scorer", "pauli_sum_set_timing", "pauli_sum_stats", "ps_last_error",
+)
+
+
+class PsError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"[{code}] {msg}")
+        self.code = code
+
+
+class ps_pauli(ctypes.Structure):
+    _fields_ = [("x", ctypes.c_uint64 * 2), ("z", ctypes.c_uint64 * 2)]
+
+
+class ps_stats(ctypes.Structure):
+    _fields_ = [(name, ctypes.c_double) for name in (
+        "updates", "gates", "rx_launches", "rx_in", "rx_out", "rx_ms", "cliff_launches", "cliff_in", "cliff_ms",
+        "sort_passes", "sort_elems", "sort_ms", "bytes_per_string")]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load liborqa_hip.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"HIP library not built: {path} (run python -m paper_2506_13241_amd.build)")
+    try:  # share torch's HIP runtime (device memory and streams come from torch)
+        import torch  # noqa: F401
+    except ImportError:  # pragma: no cover
+        pass
+    lib = ctypes.CDLL(path)
+    P, I, S, D = ctypes.c_void_p, ctypes.c_int, ctypes.c_size_t, ctypes.c_double
+    sig = {
+        "pauli_sum_create": (I, [I, I, I, S, P, P, S, P, ctypes.POINTER(P)]),
+        "pauli_sum_destroy": (I, [P]),
+        "apply_rotation_layer": (I, [P, P, P, S, D, I]),
+        "pauli_sum_gates_applied": (I, [P, ctypes.POINTER(S)]),
+        "pauli_sum_truncate": (I, [P, D, I]),
+        "expectation_z": (I, [P, P]),
+        "pauli_sum_size": (I, [P, ctypes.POINTER(S)]),
+        "pauli_sum_norm2": (I, [P, P]),
+        "pauli_sum_export": (I, [P, P, P, S, ctypes.POINTER(S)]),
+        "pauli_sum_load_scorer": (I, [P, P, S, P, S, I]),
+        "pauli_sum_set_timing": (I, [P, I]),
+        "pauli_sum_stats": (I, [P, ctypes.POINTER(ps_stats), I]),
+        "ps_last_error": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(rc: int):
+    if rc != PS_OK:
+        raise PsError(rc, load_library().ps_last_error().decode())
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _words_to_pauli(words: np.ndarray) -> np.ndarray:
+    """(m,4) uint64 words (x0,x1,z0,z1) -> (m,4) contiguous array laid out as ps_pauli."""
+    return np.ascontiguousarray(words, dtype=np.uint64).reshape(-1, 4)
+
+
+def current_stream():
+    """hipStream_t of torch's current stream (None if torch has no GPU)."""
+    try:
+        import torch
+        if torch.cuda.is_available():
+            return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    except Exception:  # pragma: no cover - torch missing
+        pass
+    return None
+
+
+class PauliSum:
+    """Handle on a GPU-resident Pauli sum (see include/orqa.h for semantics)."""
+
+    def __init__(self, n_qubits: int, terms, coeffs, dtype: int = PS_F64, capacity: int = 0, stream=None):
+        lib = load_library()
+        terms = _words_to_pauli(terms)
+        coeffs = np.ascontiguousarray(coeffs, dtype=np.float64)
+        lanes = coeffs.shape[1] if coeffs.ndim == 2 else 1
+        coeffs = coeffs.reshape(terms.shape[0], lanes)
+        self.n_qubits = n_qubits
+        self.lanes = coeffs.shape[1]
+        self.dtype = dtype
+        h = ctypes.c_void_p()
+        if stream is None:
+            stream = current_stream()
+        _check(lib.pauli_sum_create(n_qubits, self.lanes, dtype, capacity, _ptr(terms), _ptr(coeffs),
+                                    terms.shape[0], stream, ctypes.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and _lib is not None:
+            _lib.pauli_sum_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    def apply_rotation_layer(self, gates, rel_eps: float = 0.0, trunc_mode: int = PS_TRUNC_MAGNITUDE):
+        gens = _words_to_pauli(gates.gens)
+        th = np.ascontiguousarray(gates.thetas, dtype=np.float64)
+        if th.ndim == 1:
+            th = th[:, None]
+        if th.shape[1] == 1 and self.lanes > 1:
+            th = np.ascontiguousarray(np.repeat(th, self.lanes, axis=1))
+        assert th.shape == (gens.shape[0], self.lanes), th.shape
+        _check(_lib.apply_rotation_layer(self._h, _ptr(gens), _ptr(th), gens.shape[0], float(rel_eps), trunc_mode))
+        return self
+
+    def gates_applied(self) -> int:
+        n = ctypes.c_size_t()
+        _check(_lib.pauli_sum_gates_applied(self._h, ctypes.byref(n)))
+        return int(n.value)
+
+    def truncate(self, rel_eps: float, trunc_mode: int = PS_TRUNC_MAGNITUDE):
+        _check(_lib.pauli_sum_truncate(self._h, float(rel_eps), trunc_mode))
+        return self
+
+    def expectation_z(self) -> np.ndarray:
+        out = np.zeros(self.lanes)
+        _check(_lib.expectation_z(self._h, _ptr(out)))
+        return out
+
+    def size(self) -> int:
+        n = ctypes.c_size_t()
+        _check(_lib.pauli_sum_size(self._h, ctypes.byref(n)))
+        return int(n.value)
+
+    def norm2(self) -> np.ndarray:
+        out = np.zeros(self.lanes)
+        _check(_lib.pauli_sum_norm2(self._h, _ptr(out)))
+        return out
+
+    def export(self) -> tuple[np.ndarray, np.ndarray]:
+        """(terms (m,4) uint64 sorted by (x1,x0,z1,z0), coeffs (m, lanes))."""
+        n = self.size()
+        keys = np.zeros((max(n, 1), 4), dtype=np.uint64)
+        ct = np.float64 if self.dtype == PS_F64 else np.float32
+        coeffs = np.zeros((max(n, 1), self.lanes), dtype=ct)
+        got = ctypes.c_size_t()
+        _check(_lib.pauli_sum_export(self._h, _ptr(keys), _ptr(coeffs), keys.shape[0], ctypes.byref(got)))
+        m = int(got.value)
+        return keys[:m], coeffs[:m]
+
+    def set_timing(self, enable: bool = True):
+        _check(_lib.pauli_sum_set_timing(self._h, int(enable)))
+
+    def stats(self, reset: bool = False) -> dict:
+        st = ps_stats()
+        _check(_lib.pauli_sum_stats(self._h, ctypes.byref(st), int(reset)))
+        return st.as_dict()
+
+    def as_dict(self) -> dict:
+        t, c = self.export()
+        return {tuple(int(v) for v in row): c[i].copy() for i, row in enumerate(t)}
+
+
+# C-ABI names at module level (same names, same meaning).
+def pauli_sum_create(n_qubits, terms, coeffs, dtype=PS_F64, capacity=0, stream=None) -> PauliSum:
+    return PauliSum(n_qubits, terms, coeffs, dtype=dtype, capacity=capacity, stream=stream)
+
+
+def pauli_sum_destroy(ps: PauliSum):
+    ps.close()
+
+
+def apply_rotation_layer(ps: PauliSum, gates, rel_eps=0.0, trunc_mode=PS_TRUNC_MAGNITUDE):
+    return ps.apply_rotation_layer(gates, rel_eps, trunc_mode)
+
+
+def pauli_sum_truncate(ps: PauliSum, rel_eps, trunc_mode=PS_TRUNC_MAGNITUDE):
+    return ps.truncate(rel_eps, trunc_mode)
+
+
+truncate = pauli_sum_truncate
+
+
+def expectation_z(ps: PauliSum):
+    return ps.expectation_z()
+
+
+def pauli_sum_size(ps: PauliSum):
+    return ps.size()
+
+
+def pauli_sum_norm2(ps: PauliSum):
+    return ps.norm2()
+
+
+def pauli_sum_export(ps: PauliSum):
+    return ps.export()

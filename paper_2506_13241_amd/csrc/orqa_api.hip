@@ -1,0 +1,1001 @@
+// Host engine and C ABI of the gfx950 Pauli-propagation library.
+#include <algorithm>
+#include <cstdint>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/orqa.h"
+#include "orqa_internal.h"
+
+using namespace orqa;
+
+namespace {
+
+thread_local std::string g_last_error = "ok";
+
+int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                          \
+    do {                                                                                       \
+        hipError_t _e = (expr);                                                                \
+        if (_e != hipSuccess) return fail(PS_ERR_HIP, "%s: %s", #expr, hipGetErrorString(_e)); \
+    } while (0)
+
+int lanes_pad(int L) {
+    int p = 1;
+    while (p < L) p <<= 1;
+    return p;
+}
+
+// Exact trigonometry at multiples of pi/2 (within 1e-12*max(1,|theta|)).
+// Returns the multiple k mod 4, or -1 for a generic angle.
+int classify(double theta, double* c, double* s) {
+    const double half_pi = M_PI / 2.0;
+    const double k = std::nearbyint(theta / half_pi);
+    if (std::fabs(theta - k * half_pi) <= 1e-12 * std::fmax(1.0, std::fabs(theta))) {
+        long m = static_cast<long>(std::fmod(k, 4.0));
+        if (m < 0) m += 4;
+        static const double C[4] = {1.0, 0.0, -1.0, 0.0};
+        static const double S[4] = {0.0, 1.0, 0.0, -1.0};
+        *c = C[m];
+        *s = S[m];
+        return static_cast<int>(m);
+    }
+    *c = std::cos(theta);
+    *s = std::sin(theta);
+    return -1;
+}
+
+void split_f32(double v, float* hi, float* lo) {
+    *hi = static_cast<float>(v);
+    *lo = static_cast<float>(v - static_cast<double>(*hi));
+}
+
+struct U128 {
+    uint64_t lo, hi;
+};
+
+U128 rotr_host(U128 v, int r, int n) {
+    r %= n;
+    if (r == 0) return v;
+    unsigned __int128 w = (static_cast<unsigned __int128>(v.hi) << 64) | v.lo;
+    unsigned __int128 mask = (n == 128) ? ~static_cast<unsigned __int128>(0)
+                                        : ((static_cast<unsigned __int128>(1) << n) - 1);
+    w = ((w >> r) | (w << (n - r))) & mask;
+    return {static_cast<uint64_t>(w), static_cast<uint64_t>(w >> 64)};
+}
+U128 rotl_host(U128 v, int r, int n) { return rotr_host(v, (n - (r % n)) % n, n); }
+
+enum StageKind { ST_RX = 0, ST_CLIFF = 1 };
+
+struct Stage {
+    StageKind kind;
+    size_t gate_first, gate_count;  // gates of the layer covered by this stage
+    GateTrig trig;                  // RX
+    int qubit;                      // RX
+    std::vector<CliffGen> gens;     // Clifford run
+    bool needs_sort;
+};
+
+}  // namespace
+
+struct ps_handle {
+    int nq = 0, L = 1, LP = 1, dtype = PS_F64;
+    size_t csize = 8;  // bytes per coefficient row
+    size_t cap = 0;
+    Buf buf[2] = {};
+    uint32_t* rank[2] = {nullptr, nullptr};
+    Ctrl* ctrl = nullptr;
+    TileDesc* desc = nullptr;
+    uint64_t* status = nullptr;
+    size_t status_words = 0;
+    uint64_t max_tiles = 0;
+    uint32_t* hist = nullptr;
+    uint32_t* digit_base = nullptr;
+    double* partial = nullptr;
+    double* red_out = nullptr;
+    CliffGen* cgens = nullptr;
+    int cur = 0;        // state buffer holding the operator
+    int mx = 0;         // max slot of the operator
+    double pend = -1.0; // pending truncation eps of the operator (<= 0: none)
+    int xrot = 0;       // stored x = x rotated right by xrot
+    hipStream_t stream = nullptr;
+    int grid = 1024;
+    size_t gates_applied = 0;
+    uint64_t n_host = 0;  // size after the last synchronisation
+    bool broken = false;
+    // measurement: event pairs around launches, folded into host totals at syncs
+    bool timing = false;
+    std::vector<hipEvent_t> ev_pool;
+    std::vector<int> ev_kind;  // 0 rx merge, 1 clifford/compaction, 2 sort pass
+    size_t ev_used = 0;
+    double ms[3] = {0, 0, 0};
+    double sort_passes = 0, sort_elems = 0, gates = 0;
+};
+
+namespace {
+
+size_t coef_bytes(const ps_handle* h) { return h->csize; }
+
+void free_buffers(ps_handle* h) {
+    for (int b = 0; b < 2; ++b) {
+        if (h->buf[b].X) (void)hipFree(h->buf[b].X);
+        if (h->buf[b].Z) (void)hipFree(h->buf[b].Z);
+        if (h->buf[b].C) (void)hipFree(h->buf[b].C);
+        if (h->rank[b]) (void)hipFree(h->rank[b]);
+        h->buf[b] = {};
+        h->rank[b] = nullptr;
+    }
+    if (h->desc) (void)hipFree(h->desc);
+    if (h->status) (void)hipFree(h->status);
+    h->desc = nullptr;
+    h->status = nullptr;
+}
+
+// Allocate both state buffers, the rank arrays and the per-tile scratch for
+// `cap` strings.  On failure nothing is leaked and PS_ERR_CAPACITY returned.
+int alloc_buffers(ps_handle* h, size_t cap, Buf out[2], uint32_t* rk[2], TileDesc** desc, uint64_t** status,
+                  size_t* status_words, uint64_t* max_tiles) {
+    std::vector<void*> got;
+    auto grab = [&](void** p, size_t bytes) -> bool {
+        if (hipMalloc(p, bytes ? bytes : 16) != hipSuccess) {
+            (void)hipGetLastError();
+            return false;
+        }
+        got.push_back(*p);
+        return true;
+    };
+    bool ok = true;
+    for (int b = 0; b < 2 && ok; ++b) {
+        ok = grab(reinterpret_cast<void**>(&out[b].X), cap * sizeof(ulonglong2)) &&
+             grab(reinterpret_cast<void**>(&out[b].Z), cap * sizeof(ulonglong2)) &&
+             grab(&out[b].C, cap * coef_bytes(h)) && grab(reinterpret_cast<void**>(&rk[b]), cap * sizeof(uint32_t));
+    }
+    const uint64_t mt = cap / kRxTile + 4;
+    const uint64_t st_tiles = cap / kCompactTile + 4;
+    const uint64_t sort_tiles = cap / kSortTile + 4;
+    size_t words = std::max<size_t>(2 * std::max(mt, st_tiles), 256 * sort_tiles);
+    if (ok) ok = grab(reinterpret_cast<void**>(desc), (mt + 2) * sizeof(TileDesc));
+    if (ok) ok = grab(reinterpret_cast<void**>(status), words * sizeof(uint64_t));
+    if (!ok) {
+        for (void* p : got) (void)hipFree(p);
+        return fail(PS_ERR_CAPACITY, "hipMalloc failed for capacity %zu strings", cap);
+    }
+    *status_words = words;
+    *max_tiles = std::max(mt, st_tiles);
+    // status words start from a zero epoch tag the kernels never use (epoch starts at 1)
+    if (hipMemsetAsync(*status, 0, words * sizeof(uint64_t), h->stream) != hipSuccess)
+        return fail(PS_ERR_HIP, "hipMemsetAsync(status) failed");
+    return PS_OK;
+}
+
+int sync(ps_handle* h) {
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    return PS_OK;
+}
+
+int ev_collect(ps_handle* h);
+
+int read_ctrl(ps_handle* h, Ctrl* c) {
+    HIP_TRY(hipMemcpyAsync(c, h->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    return ev_collect(h);
+}
+
+// ---------------------------------------------------------------- timing
+int ev_begin(ps_handle* h, int kind, size_t* slot) {
+    *slot = SIZE_MAX;
+    if (!h->timing) return PS_OK;
+    if (h->ev_used + 2 > h->ev_pool.size()) {
+        for (int i = 0; i < 64; ++i) {
+            hipEvent_t e;
+            HIP_TRY(hipEventCreate(&e));
+            h->ev_pool.push_back(e);
+        }
+        h->ev_kind.resize(h->ev_pool.size() / 2);
+    }
+    *slot = h->ev_used;
+    h->ev_kind[h->ev_used / 2] = kind;
+    HIP_TRY(hipEventRecord(h->ev_pool[h->ev_used], h->stream));
+    h->ev_used += 2;
+    return PS_OK;
+}
+int ev_end(ps_handle* h, size_t slot) {
+    if (slot == SIZE_MAX) return PS_OK;
+    HIP_TRY(hipEventRecord(h->ev_pool[slot + 1], h->stream));
+    return PS_OK;
+}
+// Fold recorded event pairs into the totals (the stream must be synchronised).
+int ev_collect(ps_handle* h) {
+    for (size_t i = 0; i + 1 < h->ev_used; i += 2) {
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, h->ev_pool[i], h->ev_pool[i + 1]));
+        h->ms[h->ev_kind[i / 2]] += ms;
+    }
+    h->ev_used = 0;
+    return PS_OK;
+}
+
+// Grow capacity to at least `need`, keeping state buffer `keep` (front and back
+// runs) and its sizes; the other buffer's contents are discarded.
+int grow(ps_handle* h, int keep, uint64_t need) {
+    size_t ncap = std::max<size_t>(need + need / 4 + 1024, h->cap + h->cap / 2);
+    Ctrl c;
+    int rc = read_ctrl(h, &c);
+    if (rc) return rc;
+    Buf nb[2] = {};
+    uint32_t* nr[2] = {nullptr, nullptr};
+    TileDesc* nd = nullptr;
+    uint64_t* ns = nullptr;
+    size_t nw = 0;
+    uint64_t nmt = 0;
+    rc = alloc_buffers(h, ncap, nb, nr, &nd, &ns, &nw, &nmt);
+    if (rc) {
+        // retry with the bare minimum
+        ncap = need + 1024;
+        if (ncap <= h->cap) return rc;
+        rc = alloc_buffers(h, ncap, nb, nr, &nd, &ns, &nw, &nmt);
+        if (rc) return rc;
+    }
+    const uint64_t f = c.nf[keep], b = c.nb[keep];
+    const size_t cb = coef_bytes(h);
+    auto cpy = [&](void* dst, const void* src, size_t bytes) -> hipError_t {
+        return bytes ? hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, h->stream) : hipSuccess;
+    };
+    const Buf& o = h->buf[keep];
+    Buf& d = nb[keep];
+    HIP_TRY(cpy(d.X, o.X, f * sizeof(ulonglong2)));
+    HIP_TRY(cpy(d.Z, o.Z, f * sizeof(ulonglong2)));
+    HIP_TRY(cpy(d.C, o.C, f * cb));
+    HIP_TRY(cpy(d.X + (ncap - b), o.X + (h->cap - b), b * sizeof(ulonglong2)));
+    HIP_TRY(cpy(d.Z + (ncap - b), o.Z + (h->cap - b), b * sizeof(ulonglong2)));
+    HIP_TRY(cpy(static_cast<char*>(d.C) + (ncap - b) * cb, static_cast<const char*>(o.C) + (h->cap - b) * cb, b * cb));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    free_buffers(h);
+    for (int i = 0; i < 2; ++i) {
+        h->buf[i] = nb[i];
+        h->rank[i] = nr[i];
+    }
+    h->desc = nd;
+    h->status = ns;
+    h->status_words = nw;
+    h->max_tiles = nmt;
+    h->cap = ncap;
+    return PS_OK;
+}
+
+// Clear a kernel-raised capacity error so the failed stage can be re-run: the
+// failed stage left its input untouched; its output max slot is reset.
+int clear_error(ps_handle* h, int mx_out) {
+    Ctrl c;
+    int rc = read_ctrl(h, &c);
+    if (rc) return rc;
+    c.err = 0;
+    c.need = 0;
+    for (int a = 0; a < kMaxLanes; ++a) c.maxbits[mx_out][a] = 0;
+    HIP_TRY(hipMemcpyAsync(h->ctrl, &c, sizeof(Ctrl), hipMemcpyHostToDevice, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    return PS_OK;
+}
+
+int check_no_error(ps_handle* h, const char* what) {
+    Ctrl c;
+    int rc = read_ctrl(h, &c);
+    if (rc) return rc;
+    if (c.err & kErrLookback) {
+        h->broken = true;
+        return fail(PS_ERR_DEVICE, "%s: look-back wait timed out (handle is no longer usable)", what);
+    }
+    if (c.err) return fail(PS_ERR_DEVICE, "%s: kernel error bits 0x%x", what, c.err);
+    h->n_host = c.nf[h->cur] + c.nb[h->cur];
+    return PS_OK;
+}
+
+// ---------------------------------------------------------------- stages
+
+int enqueue_compact(ps_handle* h, int in, int out, int mx_in, int mx_out, double eps_in, const CliffGen* gens,
+                    int ngens, bool with_rank, int gate_count = 0) {
+    CompactArgs a{};
+    a.ctrl = h->ctrl;
+    a.in_buf = in;
+    a.out_buf = out;
+    a.mx_in = mx_in;
+    a.mx_out = mx_out;
+    a.Xin = h->buf[in].X;
+    a.Zin = h->buf[in].Z;
+    a.Cin = h->buf[in].C;
+    a.Xout = h->buf[out].X;
+    a.Zout = h->buf[out].Z;
+    a.Cout = h->buf[out].C;
+    a.rank_out = with_rank ? h->rank[out] : nullptr;
+    a.cap = h->cap;
+    a.status = h->status;
+    a.max_tiles = h->max_tiles;
+    a.eps_in = eps_in;
+    a.nq = h->nq;
+    a.xrot = h->xrot;
+    a.gens = gens;
+    a.ngens = ngens;
+    a.gate_count = gate_count;
+    size_t slot;
+    int rc = ev_begin(h, 1, &slot);
+    if (rc) return rc;
+    HIP_TRY(launch_compact(a, h->dtype, h->LP, h->stream, h->grid));
+    return ev_end(h, slot);
+}
+
+int enqueue_rx(ps_handle* h, int in, int out, int mx_in, int mx_out, double eps_in, const GateTrig& g) {
+    RxArgs a{};
+    a.ctrl = h->ctrl;
+    a.in_buf = in;
+    a.out_buf = out;
+    a.mx_in = mx_in;
+    a.mx_out = mx_out;
+    a.Xin = h->buf[in].X;
+    a.Zin = h->buf[in].Z;
+    a.Cin = h->buf[in].C;
+    a.Xout = h->buf[out].X;
+    a.Zout = h->buf[out].Z;
+    a.Cout = h->buf[out].C;
+    a.cap = h->cap;
+    a.desc = h->desc;
+    a.status = h->status;
+    a.max_tiles = h->max_tiles;
+    a.eps_in = eps_in;
+    a.nq = h->nq;
+    HIP_TRY(launch_rx_partition(a, h->stream));
+    size_t slot;
+    int rc = ev_begin(h, 0, &slot);
+    if (rc) return rc;
+    HIP_TRY(launch_rx(a, g, h->dtype, h->LP, h->stream, h->grid));
+    return ev_end(h, slot);
+}
+
+// Re-sort buffer `b` (front only, with group ranks) by (rank, z).  Returns the
+// buffer holding the result in *result.
+int sort_by_rank_z(ps_handle* h, int b, int* result) {
+    Ctrl c;
+    int rc = read_ctrl(h, &c);
+    if (rc) return rc;
+    if (c.err) return PS_OK;  // a failed stage before: nothing to sort
+    const uint64_t n = c.nf[b];
+    *result = b;
+    if (n <= 1) return PS_OK;
+    HIP_TRY(hipMemsetAsync(h->hist, 0, kSortDigits * 256 * sizeof(uint32_t), h->stream));
+    HIP_TRY(launch_sort_hist(h->ctrl, b, h->rank[b], h->buf[b].Z, h->hist, h->stream, h->grid));
+    std::vector<uint32_t> hist(kSortDigits * 256);
+    HIP_TRY(hipMemcpyAsync(hist.data(), h->hist, hist.size() * sizeof(uint32_t), hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    std::vector<int> digits;
+    for (int d = 0; d < kSortDigits; ++d) {
+        if (d < 16 && 8 * (d & 7) + 64 * (d >> 3) >= h->nq) continue;  // z byte above the register
+        int nonzero = 0;
+        for (int k = 0; k < 256; ++k) nonzero += hist[d * 256 + k] != 0;
+        if (nonzero > 1) digits.push_back(d);
+    }
+    if (digits.empty()) return PS_OK;
+    std::vector<uint32_t> bases(digits.size() * 256);
+    for (size_t i = 0; i < digits.size(); ++i) {
+        uint64_t run = 0;
+        for (int k = 0; k < 256; ++k) {
+            bases[i * 256 + k] = static_cast<uint32_t>(run);
+            run += hist[digits[i] * 256 + k];
+        }
+    }
+    HIP_TRY(hipMemcpyAsync(h->digit_base, bases.data(), bases.size() * sizeof(uint32_t), hipMemcpyHostToDevice,
+                           h->stream));
+    int src = b;
+    for (size_t i = 0; i < digits.size(); ++i) {
+        const int dst = 1 - src;
+        SortPassArgs a{};
+        a.ctrl = h->ctrl;
+        a.n = n;
+        a.digit = digits[i];
+        a.digit_base = h->digit_base + i * 256;
+        a.Rs = h->rank[src];
+        a.Zs = h->buf[src].Z;
+        a.Xs = h->buf[src].X;
+        a.Cs = h->buf[src].C;
+        a.Rd = h->rank[dst];
+        a.Zd = h->buf[dst].Z;
+        a.Xd = h->buf[dst].X;
+        a.Cd = h->buf[dst].C;
+        a.status = h->status;
+        a.max_tiles = h->status_words / 256;
+        a.dst_buf = dst;
+        size_t slot;
+        rc = ev_begin(h, 2, &slot);
+        if (rc) return rc;
+        HIP_TRY(launch_sort_pass(a, h->dtype, h->LP, h->stream, h->grid));
+        rc = ev_end(h, slot);
+        if (rc) return rc;
+        h->sort_passes += 1;
+        h->sort_elems += double(n);
+        src = dst;
+    }
+    *result = src;
+    // keep the host copy of the digit bases alive until the copy has run
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    return ev_collect(h);
+}
+
+int validate_key(int nq, const ps_pauli& p) {
+    for (int w = 0; w < 2; ++w) {
+        const int lo = w * 64;
+        if (nq >= lo + 64) continue;
+        const uint64_t allowed = (nq <= lo) ? 0ull : ((1ull << (nq - lo)) - 1ull);
+        if ((p.x[w] & ~allowed) || (p.z[w] & ~allowed)) return 0;
+    }
+    return 1;
+}
+
+// Apply the pending truncation (if any) so the state is exact as stored.
+int materialize(ps_handle* h) {
+    if (!(h->pend > 0.0)) return PS_OK;
+    const int out = 1 - h->cur, mx_out = 1 - h->mx;
+    int rc = enqueue_compact(h, h->cur, out, h->mx, mx_out, h->pend, nullptr, 0, false);
+    if (rc) return rc;
+    h->cur = out;
+    h->mx = mx_out;
+    h->pend = -1.0;
+    return check_no_error(h, "truncation");
+}
+
+int set_max_from_host(ps_handle* h, int slot, const std::vector<double>& mx) {
+    std::vector<uint64_t> bits(kMaxLanes, 0);
+    for (int a = 0; a < h->L; ++a) std::memcpy(&bits[a], &mx[a], 8);
+    HIP_TRY(hipMemcpyAsync(&h->ctrl->maxbits[slot][0], bits.data(), kMaxLanes * 8, hipMemcpyHostToDevice, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    return PS_OK;
+}
+
+}  // namespace
+
+// ================================================================ C ABI
+
+extern "C" {
+
+const char* ps_last_error(void) { return g_last_error.c_str(); }
+
+int pauli_sum_create(int n_qubits, int n_lanes, int dtype, size_t capacity, const ps_pauli* terms,
+                     const double* coeffs, size_t n_terms, void* hip_stream, ps_handle** out) {
+    if (!out) return fail(PS_ERR_INVALID, "out is NULL");
+    *out = nullptr;
+    if (n_qubits < 1 || n_qubits > 128) return fail(PS_ERR_INVALID, "n_qubits must be in 1..128");
+    if (n_lanes < 1 || n_lanes > kMaxLanes) return fail(PS_ERR_INVALID, "n_lanes must be in 1..32");
+    if (dtype != PS_F64 && dtype != PS_F32) return fail(PS_ERR_INVALID, "dtype must be PS_F64 or PS_F32");
+    if (n_terms && (!terms || !coeffs)) return fail(PS_ERR_INVALID, "terms/coeffs NULL");
+    for (size_t t = 0; t < n_terms; ++t) {
+        if (!validate_key(n_qubits, terms[t]))
+            return fail(PS_ERR_INVALID, "term %zu has bits at or above n_qubits=%d", t, n_qubits);
+        for (int a = 0; a < n_lanes; ++a)
+            if (!std::isfinite(coeffs[t * n_lanes + a]))
+                return fail(PS_ERR_NONFINITE, "coefficient %zu lane %d is not finite", t, a);
+    }
+    int dev_count = 0;
+    const hipError_t de = hipGetDeviceCount(&dev_count);
+    if (de != hipSuccess || dev_count < 1)
+        return fail(PS_ERR_HIP, "no HIP device available (%s)", hipGetErrorString(de));
+
+    ps_handle* h = new ps_handle;
+    h->nq = n_qubits;
+    h->L = n_lanes;
+    h->LP = lanes_pad(n_lanes);
+    h->dtype = dtype;
+    h->csize = size_t(h->LP) * (dtype == PS_F64 ? 8 : 4);
+    h->stream = static_cast<hipStream_t>(hip_stream);
+    {
+        int dev = 0, cus = 0;
+        (void)hipGetDevice(&dev);
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
+            h->grid = cus * 4;
+    }
+
+    // host-side canonical order: (stored x, z) ascending, duplicates summed
+    struct Row {
+        U128 x, z;
+        size_t src;
+    };
+    std::vector<Row> rows(n_terms);
+    for (size_t t = 0; t < n_terms; ++t)
+        rows[t] = {{terms[t].x[0], terms[t].x[1]}, {terms[t].z[0], terms[t].z[1]}, t};
+    auto less = [](const Row& a, const Row& b) {
+        if (a.x.hi != b.x.hi) return a.x.hi < b.x.hi;
+        if (a.x.lo != b.x.lo) return a.x.lo < b.x.lo;
+        if (a.z.hi != b.z.hi) return a.z.hi < b.z.hi;
+        return a.z.lo < b.z.lo;
+    };
+    std::stable_sort(rows.begin(), rows.end(), less);
+    std::vector<ulonglong2> hx, hz;
+    std::vector<double> hc;
+    for (size_t i = 0; i < rows.size(); ++i) {
+        const Row& r = rows[i];
+        if (!hx.empty() && hx.back().x == r.x.lo && hx.back().y == r.x.hi && hz.back().x == r.z.lo &&
+            hz.back().y == r.z.hi) {
+            for (int a = 0; a < n_lanes; ++a) hc[(hx.size() - 1) * h->LP + a] += coeffs[r.src * n_lanes + a];
+            continue;
+        }
+        hx.push_back(make_ulonglong2(r.x.lo, r.x.hi));
+        hz.push_back(make_ulonglong2(r.z.lo, r.z.hi));
+        for (int a = 0; a < h->LP; ++a) hc.push_back(a < n_lanes ? coeffs[r.src * n_lanes + a] : 0.0);
+    }
+    const size_t n = hx.size();
+    size_t cap = std::max<size_t>({capacity, n + 1024, size_t(1) << 16});
+    h->cap = cap;
+    int rc = PS_OK;
+    auto bail = [&](int code) {
+        free_buffers(h);
+        if (h->ctrl) (void)hipFree(h->ctrl);
+        if (h->hist) (void)hipFree(h->hist);
+        if (h->digit_base) (void)hipFree(h->digit_base);
+        if (h->partial) (void)hipFree(h->partial);
+        if (h->red_out) (void)hipFree(h->red_out);
+        if (h->cgens) (void)hipFree(h->cgens);
+        delete h;
+        return code;
+    };
+    if (hipMalloc(reinterpret_cast<void**>(&h->ctrl), sizeof(Ctrl)) != hipSuccess ||
+        hipMalloc(reinterpret_cast<void**>(&h->hist), kSortDigits * 256 * sizeof(uint32_t)) != hipSuccess ||
+        hipMalloc(reinterpret_cast<void**>(&h->digit_base), kSortDigits * 256 * sizeof(uint32_t)) != hipSuccess ||
+        hipMalloc(reinterpret_cast<void**>(&h->partial), kReduceBlocks * kMaxLanes * sizeof(double)) != hipSuccess ||
+        hipMalloc(reinterpret_cast<void**>(&h->red_out), kMaxLanes * sizeof(double)) != hipSuccess ||
+        hipMalloc(reinterpret_cast<void**>(&h->cgens), kMaxCliffGens * sizeof(CliffGen)) != hipSuccess) {
+        (void)hipGetLastError();
+        return bail(fail(PS_ERR_CAPACITY, "hipMalloc failed for handle scratch"));
+    }
+    rc = alloc_buffers(h, cap, h->buf, h->rank, &h->desc, &h->status, &h->status_words, &h->max_tiles);
+    if (rc) return bail(rc);
+    Ctrl c;
+    std::memset(&c, 0, sizeof c);
+    c.epoch = 1;
+    c.nf[0] = n;
+    std::vector<double> mx(kMaxLanes, 0.0);
+    for (size_t i = 0; i < n; ++i)
+        for (int a = 0; a < n_lanes; ++a) mx[a] = std::fmax(mx[a], std::fabs(hc[i * h->LP + a]));
+    for (int a = 0; a < n_lanes; ++a) std::memcpy(&c.maxbits[0][a], &mx[a], 8);
+    if (hipMemcpyAsync(h->ctrl, &c, sizeof c, hipMemcpyHostToDevice, h->stream) != hipSuccess)
+        return bail(fail(PS_ERR_HIP, "upload ctrl"));
+    if (n) {
+        if (hipMemcpyAsync(h->buf[0].X, hx.data(), n * sizeof(ulonglong2), hipMemcpyHostToDevice, h->stream) !=
+                hipSuccess ||
+            hipMemcpyAsync(h->buf[0].Z, hz.data(), n * sizeof(ulonglong2), hipMemcpyHostToDevice, h->stream) !=
+                hipSuccess)
+            return bail(fail(PS_ERR_HIP, "upload keys"));
+        if (dtype == PS_F64) {
+            if (hipMemcpyAsync(h->buf[0].C, hc.data(), n * h->LP * 8, hipMemcpyHostToDevice, h->stream) != hipSuccess)
+                return bail(fail(PS_ERR_HIP, "upload coefficients"));
+            if (hipStreamSynchronize(h->stream) != hipSuccess) return bail(fail(PS_ERR_HIP, "sync"));
+        } else {
+            std::vector<float> f(hc.size());
+            for (size_t i = 0; i < hc.size(); ++i) f[i] = static_cast<float>(hc[i]);
+            if (hipMemcpyAsync(h->buf[0].C, f.data(), f.size() * 4, hipMemcpyHostToDevice, h->stream) != hipSuccess)
+                return bail(fail(PS_ERR_HIP, "upload coefficients"));
+            if (hipStreamSynchronize(h->stream) != hipSuccess) return bail(fail(PS_ERR_HIP, "sync"));
+        }
+    }
+    if (hipStreamSynchronize(h->stream) != hipSuccess) return bail(fail(PS_ERR_HIP, "sync"));
+    h->n_host = n;
+    *out = h;
+    return PS_OK;
+}
+
+int pauli_sum_destroy(ps_handle* h) {
+    if (!h) return PS_OK;
+    (void)hipStreamSynchronize(h->stream);
+    free_buffers(h);
+    if (h->ctrl) (void)hipFree(h->ctrl);
+    if (h->hist) (void)hipFree(h->hist);
+    if (h->digit_base) (void)hipFree(h->digit_base);
+    if (h->partial) (void)hipFree(h->partial);
+    if (h->red_out) (void)hipFree(h->red_out);
+    if (h->cgens) (void)hipFree(h->cgens);
+    for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
+    delete h;
+    return PS_OK;
+}
+
+int pauli_sum_gates_applied(ps_handle* h, size_t* n) {
+    if (!h || !n) return fail(PS_ERR_INVALID, "NULL argument");
+    *n = h->gates_applied;
+    return PS_OK;
+}
+
+int apply_rotation_layer(ps_handle* h, const ps_pauli* gens, const double* thetas, size_t n_gates, double rel_eps,
+                         int trunc_mode) {
+    if (!h) return fail(PS_ERR_INVALID, "handle is NULL");
+    if (h->broken) return fail(PS_ERR_DEVICE, "handle is no longer usable after a device failure");
+    h->gates_applied = 0;
+    if (n_gates == 0) return PS_OK;
+    if (!gens || !thetas) return fail(PS_ERR_INVALID, "gens/thetas NULL");
+    if (trunc_mode != PS_TRUNC_NONE && trunc_mode != PS_TRUNC_MAGNITUDE && trunc_mode != PS_TRUNC_LEARNED)
+        return fail(PS_ERR_INVALID, "unknown trunc_mode %d", trunc_mode);
+    if (trunc_mode == PS_TRUNC_LEARNED) return fail(PS_ERR_UNSUPPORTED, "learned truncation is not built in this library");
+    if (std::isnan(rel_eps)) return fail(PS_ERR_NONFINITE, "rel_eps is NaN");
+    const double eps = (trunc_mode == PS_TRUNC_NONE || !(rel_eps > 0.0)) ? -1.0 : rel_eps;
+    for (size_t g = 0; g < n_gates; ++g) {
+        if (!validate_key(h->nq, gens[g])) return fail(PS_ERR_INVALID, "generator %zu has bits above n_qubits", g);
+        for (int a = 0; a < h->L; ++a)
+            if (!std::isfinite(thetas[g * h->L + a])) return fail(PS_ERR_NONFINITE, "theta %zu lane %d", g, a);
+    }
+
+    // ---- plan: runs of Z-only Clifford gates, and sigma_x rotations on the
+    // qubit at stored bit 0.
+    std::vector<Stage> stages;
+    int xrot = h->xrot;
+    for (size_t g = 0; g < n_gates;) {
+        const ps_pauli& G = gens[g];
+        double cs[kMaxLanes], sn[kMaxLanes];
+        int kk[kMaxLanes];
+        bool same_k = true;
+        for (int a = 0; a < h->L; ++a) {
+            kk[a] = classify(thetas[g * h->L + a], &cs[a], &sn[a]);
+            if (kk[a] != kk[0]) same_k = false;
+        }
+        const bool zonly = (G.x[0] | G.x[1]) == 0;
+        const bool zero = zonly && (G.z[0] | G.z[1]) == 0;
+        if (zero) {  // identity generator: the gate is a global phase
+            Stage s{};
+            s.kind = ST_CLIFF;
+            s.gate_first = g;
+            s.gate_count = 1;
+            s.needs_sort = false;
+            stages.push_back(s);
+            ++g;
+            continue;
+        }
+        if (zonly && same_k && kk[0] >= 0) {
+            Stage s{};
+            s.kind = ST_CLIFF;
+            s.gate_first = g;
+            s.needs_sort = false;
+            size_t e = g;
+            while (e < n_gates && s.gens.size() < size_t(kMaxCliffGens)) {
+                const ps_pauli& E = gens[e];
+                if ((E.x[0] | E.x[1]) != 0) break;
+                double c2[kMaxLanes], s2[kMaxLanes];
+                int k0 = -2;
+                bool ok = true;
+                for (int a = 0; a < h->L; ++a) {
+                    const int k = classify(thetas[e * h->L + a], &c2[a], &s2[a]);
+                    if (a == 0) k0 = k;
+                    if (k != k0) ok = false;
+                }
+                if (!ok || k0 < 0) break;
+                if (k0 != 0 && (E.z[0] | E.z[1]) != 0) {
+                    CliffGen cg{};
+                    cg.z0 = E.z[0];
+                    cg.z1 = E.z[1];
+                    cg.kodd = (k0 & 1) ? 1u : 0u;
+                    cg.neg = (k0 == 3 || k0 == 2) ? 1u : 0u;
+                    s.gens.push_back(cg);
+                    if (cg.kodd) s.needs_sort = true;
+                }
+                ++e;
+            }
+            s.gate_count = e - g;
+            stages.push_back(std::move(s));
+            g = e;
+            continue;
+        }
+        // sigma_x on one qubit?
+        const bool single_x = (G.z[0] | G.z[1]) == 0 && (__builtin_popcountll(G.x[0]) + __builtin_popcountll(G.x[1])) == 1;
+        if (single_x) {
+            const int q = G.x[0] ? __builtin_ctzll(G.x[0]) : 64 + __builtin_ctzll(G.x[1]);
+            if (q == xrot % h->nq) {
+                Stage s{};
+                s.kind = ST_RX;
+                s.gate_first = g;
+                s.gate_count = 1;
+                s.qubit = q;
+                GateTrig& t = s.trig;
+                std::memset(&t, 0, sizeof t);
+                bool any_c = false, any_s = false;
+                for (int a = 0; a < h->L; ++a) {
+                    t.cs[a] = cs[a];
+                    t.sn[a] = sn[a];
+                    split_f32(cs[a], &t.cs_hi[a], &t.cs_lo[a]);
+                    split_f32(sn[a], &t.sn_hi[a], &t.sn_lo[a]);
+                    any_c |= cs[a] != 0.0;
+                    any_s |= sn[a] != 0.0;
+                }
+                t.any_c = any_c;
+                t.any_s = any_s;
+                t.zword = q >> 6;
+                t.zbit = q & 63;
+                stages.push_back(s);
+                xrot = (xrot + 1) % h->nq;
+                ++g;
+                continue;
+            }
+        }
+        return fail(PS_ERR_UNSUPPORTED,
+                    "gate %zu: only Z-only Clifford runs and sigma_x rotations on consecutive qubits "
+                    "(expected qubit %d) are built",
+                    g, xrot % h->nq);
+    }
+
+    // ---- execute.  Stages are enqueued back to back; the host synchronises
+    // after a Clifford stage that needs a re-sort and at the end.  A stage
+    // that runs out of capacity raises kErrCapacity, every later kernel turns
+    // into a no-op, and the stage's input buffer is intact: grow and resume.
+    Ctrl c0;
+    int rc = read_ctrl(h, &c0);
+    if (rc) return rc;
+    if (c0.err) return fail(PS_ERR_DEVICE, "device error bits 0x%x before the layer", c0.err);
+    const uint64_t zero64 = 0;
+    HIP_TRY(hipMemcpyAsync(&h->ctrl->stages_done, &zero64, 8, hipMemcpyHostToDevice, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+
+    struct Launched {
+        size_t stage;
+        int cur, mx, xrot;
+        double pend;
+    };
+    size_t si = 0;
+    while (si < stages.size()) {
+        std::vector<Launched> launched;
+        bool sort_after = false;
+        for (; si < stages.size(); ++si) {
+            Stage& s = stages[si];
+            const bool noop = s.kind == ST_CLIFF && s.gens.empty() && !(h->pend > 0.0);
+            if (noop) {
+                // the gates leave every magnitude (and the max) unchanged:
+                // only the pending threshold of this layer is recorded
+                if (eps > 0.0) h->pend = std::max(h->pend, eps);
+                continue;
+            }
+            launched.push_back({si, h->cur, h->mx, h->xrot, h->pend});
+            const int in = h->cur, out = 1 - h->cur, mx_in = h->mx, mx_out = 1 - h->mx;
+            if (s.kind == ST_RX) {
+                rc = enqueue_rx(h, in, out, mx_in, mx_out, h->pend, s.trig);
+                if (rc) return rc;
+                h->xrot = (h->xrot + 1) % h->nq;
+            } else {
+                if (!s.gens.empty())
+                    HIP_TRY(hipMemcpyAsync(h->cgens, s.gens.data(), s.gens.size() * sizeof(CliffGen),
+                                           hipMemcpyHostToDevice, h->stream));
+                rc = enqueue_compact(h, in, out, mx_in, mx_out, h->pend, h->cgens, int(s.gens.size()),
+                                     s.needs_sort, int(s.gate_count));
+                if (rc) return rc;
+                if (!s.gens.empty()) HIP_TRY(hipStreamSynchronize(h->stream));  // cgens reused by the next run
+            }
+            h->cur = out;
+            h->mx = mx_out;
+            h->pend = eps;
+            if (s.kind == ST_CLIFF && s.needs_sort) {
+                sort_after = true;
+                ++si;
+                break;
+            }
+        }
+        Ctrl c;
+        rc = read_ctrl(h, &c);
+        if (rc) return rc;
+        if (c.err & kErrLookback) {
+            h->broken = true;
+            return fail(PS_ERR_DEVICE, "look-back wait timed out (handle is no longer usable)");
+        }
+        if (c.err & kErrCapacity) {
+            if (c.stages_done >= launched.size())
+                return fail(PS_ERR_DEVICE, "capacity error with no failing stage");
+            const Launched& L = launched[c.stages_done];
+            h->cur = L.cur;
+            h->mx = L.mx;
+            h->xrot = L.xrot;
+            h->pend = L.pend;
+            const int grc = grow(h, h->cur, c.need);
+            rc = clear_error(h, 1 - h->mx);
+            HIP_TRY(hipMemcpyAsync(&h->ctrl->stages_done, &zero64, 8, hipMemcpyHostToDevice, h->stream));
+            HIP_TRY(hipStreamSynchronize(h->stream));
+            if (grc) {
+                h->gates_applied = stages[L.stage].gate_first;
+                return grc;
+            }
+            if (rc) return rc;
+            si = L.stage;
+            continue;
+        }
+        if (c.err) return fail(PS_ERR_DEVICE, "kernel error bits 0x%x", c.err);
+        HIP_TRY(hipMemcpyAsync(&h->ctrl->stages_done, &zero64, 8, hipMemcpyHostToDevice, h->stream));
+        h->n_host = c.nf[h->cur] + c.nb[h->cur];
+        if (sort_after) {
+            int res = h->cur;
+            rc = sort_by_rank_z(h, h->cur, &res);
+            if (rc) return rc;
+            h->cur = res;
+            rc = check_no_error(h, "re-sort");
+            if (rc) return rc;
+        }
+        h->gates_applied = (si < stages.size()) ? stages[si].gate_first : n_gates;
+        // grow ahead of a layer when the operator is close to the capacity
+        if (si < stages.size() && h->n_host + h->n_host / 3 + 1024 > h->cap) {
+            rc = grow(h, h->cur, h->n_host + h->n_host / 3 + 1024);
+            if (rc && rc != PS_ERR_CAPACITY) return rc;
+        }
+    }
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    h->gates_applied = n_gates;
+    h->gates += double(n_gates);
+    return PS_OK;
+}
+
+int pauli_sum_truncate(ps_handle* h, double rel_eps, int trunc_mode) {
+    if (!h) return fail(PS_ERR_INVALID, "handle is NULL");
+    if (h->broken) return fail(PS_ERR_DEVICE, "handle is no longer usable");
+    if (trunc_mode == PS_TRUNC_LEARNED) return fail(PS_ERR_UNSUPPORTED, "learned truncation is not built in this library");
+    int rc = materialize(h);
+    if (rc) return rc;
+    if (trunc_mode == PS_TRUNC_NONE || !(rel_eps > 0.0)) return PS_OK;
+    h->pend = rel_eps;
+    return materialize(h);
+}
+
+int expectation_z(ps_handle* h, double* out) {
+    if (!h || !out) return fail(PS_ERR_INVALID, "NULL argument");
+    if (h->broken) return fail(PS_ERR_DEVICE, "handle is no longer usable");
+    int rc = materialize(h);
+    if (rc) return rc;
+    HIP_TRY(launch_reduce(h->ctrl, h->cur, h->buf[h->cur].X, h->buf[h->cur].C, h->cap, 0, h->partial, h->red_out,
+                          h->dtype, h->LP, h->L, h->stream));
+    double tmp[kMaxLanes];
+    HIP_TRY(hipMemcpyAsync(tmp, h->red_out, h->LP * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    for (int a = 0; a < h->L; ++a) out[a] = tmp[a];
+    return PS_OK;
+}
+
+int pauli_sum_norm2(ps_handle* h, double* out) {
+    if (!h || !out) return fail(PS_ERR_INVALID, "NULL argument");
+    if (h->broken) return fail(PS_ERR_DEVICE, "handle is no longer usable");
+    int rc = materialize(h);
+    if (rc) return rc;
+    HIP_TRY(launch_reduce(h->ctrl, h->cur, h->buf[h->cur].X, h->buf[h->cur].C, h->cap, 1, h->partial, h->red_out,
+                          h->dtype, h->LP, h->L, h->stream));
+    double tmp[kMaxLanes];
+    HIP_TRY(hipMemcpyAsync(tmp, h->red_out, h->LP * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    for (int a = 0; a < h->L; ++a) out[a] = tmp[a];
+    return PS_OK;
+}
+
+int pauli_sum_size(ps_handle* h, size_t* n) {
+    if (!h || !n) return fail(PS_ERR_INVALID, "NULL argument");
+    if (h->broken) return fail(PS_ERR_DEVICE, "handle is no longer usable");
+    int rc = materialize(h);
+    if (rc) return rc;
+    Ctrl c;
+    rc = read_ctrl(h, &c);
+    if (rc) return rc;
+    *n = c.nf[h->cur] + c.nb[h->cur];
+    return PS_OK;
+}
+
+int pauli_sum_export(ps_handle* h, ps_pauli* keys, void* coeffs, size_t cap, size_t* n) {
+    if (!h || !n) return fail(PS_ERR_INVALID, "NULL argument");
+    if (h->broken) return fail(PS_ERR_DEVICE, "handle is no longer usable");
+    int rc = materialize(h);
+    if (rc) return rc;
+    Ctrl c;
+    rc = read_ctrl(h, &c);
+    if (rc) return rc;
+    const uint64_t f = c.nf[h->cur], b = c.nb[h->cur];
+    *n = f + b;
+    if (f + b > cap) return fail(PS_ERR_CAPACITY, "export buffer holds %zu strings, %llu needed", cap,
+                                 static_cast<unsigned long long>(f + b));
+    if (f + b == 0) return PS_OK;
+    if (!keys || !coeffs) return fail(PS_ERR_INVALID, "keys/coeffs NULL");
+    std::vector<ulonglong2> X(f + b), Z(f + b);
+    const size_t cb = coef_bytes(h);
+    std::vector<char> C((f + b) * cb);
+    const Buf& B = h->buf[h->cur];
+    if (f) {
+        HIP_TRY(hipMemcpyAsync(X.data(), B.X, f * 16, hipMemcpyDeviceToHost, h->stream));
+        HIP_TRY(hipMemcpyAsync(Z.data(), B.Z, f * 16, hipMemcpyDeviceToHost, h->stream));
+        HIP_TRY(hipMemcpyAsync(C.data(), B.C, f * cb, hipMemcpyDeviceToHost, h->stream));
+    }
+    if (b) {
+        HIP_TRY(hipMemcpyAsync(X.data() + f, B.X + (h->cap - b), b * 16, hipMemcpyDeviceToHost, h->stream));
+        HIP_TRY(hipMemcpyAsync(Z.data() + f, B.Z + (h->cap - b), b * 16, hipMemcpyDeviceToHost, h->stream));
+        HIP_TRY(hipMemcpyAsync(C.data() + f * cb, static_cast<const char*>(B.C) + (h->cap - b) * cb, b * cb,
+                               hipMemcpyDeviceToHost, h->stream));
+    }
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    // back run is stored descending
+    std::reverse(X.begin() + f, X.end());
+    std::reverse(Z.begin() + f, Z.end());
+    for (uint64_t i = 0; i < b / 2; ++i)
+        std::swap_ranges(C.begin() + (f + i) * cb, C.begin() + (f + i + 1) * cb, C.begin() + (f + b - 1 - i) * cb);
+    struct Row {
+        U128 x, z;
+        uint64_t i;
+    };
+    std::vector<Row> rows(f + b);
+    for (uint64_t i = 0; i < f + b; ++i) {
+        rows[i].x = rotl_host({X[i].x, X[i].y}, h->xrot, h->nq);
+        rows[i].z = {Z[i].x, Z[i].y};
+        rows[i].i = i;
+    }
+    if (h->xrot != 0) {
+        std::sort(rows.begin(), rows.end(), [](const Row& a, const Row& bb) {
+            if (a.x.hi != bb.x.hi) return a.x.hi < bb.x.hi;
+            if (a.x.lo != bb.x.lo) return a.x.lo < bb.x.lo;
+            if (a.z.hi != bb.z.hi) return a.z.hi < bb.z.hi;
+            return a.z.lo < bb.z.lo;
+        });
+    }
+    const size_t es = (h->dtype == PS_F64) ? 8 : 4;
+    char* dst = static_cast<char*>(coeffs);
+    for (uint64_t i = 0; i < f + b; ++i) {
+        const Row& r = rows[i];
+        keys[i].x[0] = r.x.lo;
+        keys[i].x[1] = r.x.hi;
+        keys[i].z[0] = r.z.lo;
+        keys[i].z[1] = r.z.hi;
+        std::memcpy(dst + i * h->L * es, C.data() + r.i * cb, h->L * es);
+    }
+    return PS_OK;
+}
+
+int pauli_sum_set_timing(ps_handle* h, int enable) {
+    if (!h) return fail(PS_ERR_INVALID, "handle is NULL");
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    int rc = ev_collect(h);
+    if (rc) return rc;
+    h->timing = enable != 0;
+    return PS_OK;
+}
+
+int pauli_sum_stats(ps_handle* h, ps_stats* out, int reset) {
+    if (!h || !out) return fail(PS_ERR_INVALID, "NULL argument");
+    Ctrl c;
+    int rc = read_ctrl(h, &c);
+    if (rc) return rc;
+    out->updates = double(c.cnt_updates);
+    out->gates = h->gates;
+    out->rx_launches = double(c.cnt_rx_launches);
+    out->rx_in = double(c.cnt_rx_in);
+    out->rx_out = double(c.cnt_rx_out);
+    out->rx_ms = h->ms[0];
+    out->cliff_launches = double(c.cnt_cliff_launches);
+    out->cliff_in = double(c.cnt_cliff_in);
+    out->cliff_ms = h->ms[1];
+    out->sort_passes = h->sort_passes;
+    out->sort_elems = h->sort_elems;
+    out->sort_ms = h->ms[2];
+    out->bytes_per_string = double(2 * sizeof(ulonglong2) + h->csize);
+    if (reset) {
+        c.cnt_updates = c.cnt_rx_in = c.cnt_rx_out = c.cnt_rx_launches = 0;
+        c.cnt_cliff_in = c.cnt_cliff_launches = 0;
+        HIP_TRY(hipMemcpyAsync(&h->ctrl->cnt_updates, &c.cnt_updates, 6 * sizeof(uint64_t), hipMemcpyHostToDevice,
+                               h->stream));
+        HIP_TRY(hipStreamSynchronize(h->stream));
+        h->ms[0] = h->ms[1] = h->ms[2] = 0;
+        h->sort_passes = h->sort_elems = h->gates = 0;
+    }
+    return PS_OK;
+}
+
+int pauli_sum_load_scorer(ps_handle* h, const uint16_t* bf16_w, size_t n_w, const float* f32_b, size_t n_b,
+                          int obs_qubit) {
+    (void)bf16_w;
+    (void)n_w;
+    (void)f32_b;
+    (void)n_b;
+    (void)obs_qubit;
+    if (!h) return fail(PS_ERR_INVALID, "handle is NULL");
+    return fail(PS_ERR_UNSUPPORTED, "learned truncation is not built in this library");
+}
+
+}  // extern "C"

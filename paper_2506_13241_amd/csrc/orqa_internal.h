@@ -1,0 +1,152 @@
+// Internal types shared by the gfx950 kernels and the host engine.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <cstdint>
+
+namespace orqa {
+
+constexpr int kMaxLanes = 32;
+constexpr int kMaxCliffGens = 512;  // Clifford generators fused into one pass
+
+// Error bits raised by kernels in Ctrl::err.
+constexpr uint32_t kErrCapacity = 1u;
+constexpr uint32_t kErrLookback = 2u;
+constexpr uint32_t kErrInternal = 4u;  // inconsistent tile split (never expected)
+
+// Tile sizes.  An RX tile covers kRxTile merged positions; pair-preserving
+// boundary adjustment can move either end by one, so a tile holds at most
+// kRxTile + 1 <= kRxTileMax strings.
+constexpr int kThreads = 256;
+constexpr int kRxIPT = 4;
+constexpr int kRxTileMax = kThreads * kRxIPT;  // 1024
+constexpr int kRxTile = kRxTileMax - 2;        // 1022
+constexpr int kCompactIPT = 4;
+constexpr int kCompactTile = kThreads * kCompactIPT;  // 1024
+constexpr int kSortIPT = 8;
+constexpr int kSortTile = kThreads * kSortIPT;  // 2048
+constexpr int kSortDigits = 20;                 // 16 byte digits of z, 4 of the group rank
+constexpr int kReduceBlocks = 512;
+
+// Device-resident control block of a handle.  The two state buffers each hold
+// a "virtual array": a front run at [0, nf) ascending and a back run stored
+// descending from the end of the buffer, [cap-nb, cap).  Logical element i is
+// physical i for i < nf and cap-1-(i-nf) otherwise.
+struct Ctrl {
+    uint64_t nf[2];
+    uint64_t nb[2];
+    uint64_t maxbits[2][kMaxLanes];  // max |c| per lane as binary64 bits, two slots
+    uint32_t tile_counter;           // dynamic tile index of the running look-back kernel
+    uint32_t done_counter;           // workgroups finished (last one resets the two counters)
+    uint32_t epoch;                  // look-back status generation, bumped per look-back launch
+    uint32_t err;                    // kErr* bits
+    uint64_t need;                   // strings a failed stage needed
+    uint64_t stages_done;            // stages finished without error since the host reset it
+    uint64_t prefix_len;             // length of the x == 0 prefix (expectation)
+    uint64_t nranks;                 // x-groups counted by the last Clifford pass
+    uint64_t cnt_updates;            // sum over gates of strings read
+    uint64_t cnt_rx_in, cnt_rx_out, cnt_rx_launches;
+    uint64_t cnt_cliff_in, cnt_cliff_launches;
+    uint64_t aux[4];
+};
+
+// Tile boundary of an RX merge: the split of merged position b.
+struct TileDesc {
+    uint64_t posA, posB, hm, he;
+};
+
+// Per-gate trigonometry (per lane), exact at Clifford angles.  The fp32 form
+// splits each value into hi + lo.
+struct GateTrig {
+    double cs[kMaxLanes], sn[kMaxLanes];
+    float cs_hi[kMaxLanes], cs_lo[kMaxLanes], sn_hi[kMaxLanes], sn_lo[kMaxLanes];
+    int any_c, any_s;
+    int zword, zbit;  // location of z_j of the rotated qubit j
+};
+
+// A Z-only Clifford generator: z mask and the action on anticommuting strings.
+// kodd: theta = +-pi/2 (mod 2pi): key becomes K = I xor J with factor
+// sign(B(K,J)) * sin(theta); otherwise theta = pi (mod 2pi): factor -1.
+struct CliffGen {
+    uint64_t z0, z1;
+    uint32_t kodd;
+    uint32_t neg;  // kodd: sin(theta) = -1; else: cos(theta) = -1
+};
+
+struct Buf {
+    ulonglong2* X;  // stored (rotated) x mask
+    ulonglong2* Z;
+    void* C;        // cap x lanes_pad coefficients
+};
+
+struct RxArgs {
+    Ctrl* ctrl;
+    int in_buf, out_buf, mx_in, mx_out;
+    const ulonglong2* Xin;
+    const ulonglong2* Zin;
+    const void* Cin;
+    ulonglong2* Xout;
+    ulonglong2* Zout;
+    void* Cout;
+    uint64_t cap;
+    TileDesc* desc;
+    uint64_t* status;  // 2 x max_tiles
+    uint64_t max_tiles;
+    double eps_in;     // pending truncation of the input (<= 0: none)
+    int nq;
+    // learned truncation (eps_in applies to |c| * g(features) when scorer != null)
+    const void* scorer;
+};
+
+struct CompactArgs {
+    Ctrl* ctrl;
+    int in_buf, out_buf, mx_in, mx_out;
+    const ulonglong2* Xin;
+    const ulonglong2* Zin;
+    const void* Cin;
+    ulonglong2* Xout;
+    ulonglong2* Zout;
+    void* Cout;
+    uint32_t* rank_out;  // may be null
+    uint64_t cap;
+    uint64_t* status;    // 2 x max_tiles
+    uint64_t max_tiles;
+    double eps_in;
+    int nq, xrot;
+    const CliffGen* gens;
+    int ngens;
+    int gate_count;      // gates this pass stands for (measurement counters)
+    const void* scorer;
+};
+
+struct SortPassArgs {
+    Ctrl* ctrl;
+    uint64_t n;
+    int digit;               // 0..15: byte of z (low word first), 16..19: byte of rank
+    const uint32_t* digit_base;  // 256 exclusive bucket starts for this digit
+    const uint32_t* Rs;
+    const ulonglong2* Zs;
+    const ulonglong2* Xs;
+    const void* Cs;
+    uint32_t* Rd;
+    ulonglong2* Zd;
+    ulonglong2* Xd;
+    void* Cd;
+    uint64_t* status;        // max_tiles x 256
+    uint64_t max_tiles;
+    int dst_buf;
+};
+
+// Host-side launchers (orqa_kernels.hip), dispatching on dtype and padded lanes.
+hipError_t launch_rx_partition(const RxArgs& a, hipStream_t s);
+hipError_t launch_rx(const RxArgs& a, const GateTrig& g, int dtype, int lp, hipStream_t s, int grid);
+hipError_t launch_compact(const CompactArgs& a, int dtype, int lp, hipStream_t s, int grid);
+hipError_t launch_sort_hist(Ctrl* ctrl, int buf, const uint32_t* R, const ulonglong2* Z, uint32_t* hist,
+                            hipStream_t s, int grid);
+hipError_t launch_sort_pass(const SortPassArgs& a, int dtype, int lp, hipStream_t s, int grid);
+hipError_t launch_reduce(Ctrl* ctrl, int buf, const ulonglong2* X, const void* C, uint64_t cap, int mode,
+                         double* partial, double* out, int dtype, int lp, int lanes, hipStream_t s);
+hipError_t launch_fill_u64(uint64_t* p, uint64_t v, size_t n, hipStream_t s);
+
+}  // namespace orqa

@@ -1,0 +1,839 @@
+// gfx950 kernels of the Heisenberg Pauli-propagation hot path.
+//
+// Layout: the live operator is kept sorted by (X, z), X being the x mask stored
+// rotated right by the number of sigma_x rotations applied so far in the
+// current layer, so that the qubit of the next RX gate always sits at stored
+// bit 0.  For a sigma_x generator on that qubit, a string and its partner
+// I xor J differ in stored bit 0 only: they lie in two adjacent x-groups
+// (the "A" group with bit 0 clear and the "B" group with bit 0 set) of one
+// pairing block, at the same z.  One gate (Eq. update_rule, Algorithm 1 gate
+// loop + apply-received loop) is therefore a merge by z of the two groups of
+// every block; the outputs with x_j = 0 go to the front run of the output
+// buffer and those with x_j = 1 to its back run, which yields the next gate's
+// order (stored x rotated by one more bit) without any sort.
+#include "orqa_device.h"
+
+namespace orqa {
+
+// ================================================================ RX: tile split
+// Sorted order of the input: (X, z).  A pairing block = equal X with bit 0
+// cleared.  Merged order inside a block: by z, A before B on ties, so a
+// string and its partner are adjacent.  split(b) returns the input positions
+// where merged position b falls, moved by one when b would separate a pair.
+
+struct VIn {
+    const ulonglong2* X;
+    const ulonglong2* Z;
+    uint64_t nf, cap;
+    __device__ __forceinline__ ulonglong2 x(uint64_t i) const { return X[vphys(i, nf, cap)]; }
+    __device__ __forceinline__ ulonglong2 z(uint64_t i) const { return Z[vphys(i, nf, cap)]; }
+};
+
+// first i in [lo, hi) with h(X[i]) >= key (hi if none)
+__device__ uint64_t first_h_geq(const VIn& v, ulonglong2 key, uint64_t lo, uint64_t hi) {
+    while (lo < hi) {
+        const uint64_t mid = lo + (hi - lo) / 2;
+        if (k_lt(k_h(v.x(mid)), key)) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+// first i in [lo, hi) with h(X[i]) > key
+__device__ uint64_t first_h_gt(const VIn& v, ulonglong2 key, uint64_t lo, uint64_t hi) {
+    while (lo < hi) {
+        const uint64_t mid = lo + (hi - lo) / 2;
+        if (k_le(k_h(v.x(mid)), key)) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+// first i in [lo, hi) with X[i] >= key
+__device__ uint64_t first_x_geq(const VIn& v, ulonglong2 key, uint64_t lo, uint64_t hi) {
+    while (lo < hi) {
+        const uint64_t mid = lo + (hi - lo) / 2;
+        if (k_lt(v.x(mid), key)) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+__device__ TileDesc rx_split(const VIn& v, uint64_t n, uint64_t b) {
+    if (b >= n) return {n, n, n, n};
+    const ulonglong2 H = k_h(v.x(b));
+    // block start: gallop backwards
+    uint64_t r = b, lo;
+    for (uint64_t step = 1;; step <<= 1) {
+        if (r < step) {
+            lo = 0;
+            break;
+        }
+        const uint64_t c = r - step;
+        if (k_lt(k_h(v.x(c)), H)) {
+            lo = c + 1;
+            break;
+        }
+        r = c;
+    }
+    const uint64_t hs = first_h_geq(v, H, lo, r);
+    // block end: gallop forwards
+    uint64_t l = b, hi;
+    for (uint64_t step = 1;; step <<= 1) {
+        const uint64_t c = l + step;
+        if (c >= n) {
+            hi = n;
+            break;
+        }
+        if (k_lt(H, k_h(v.x(c)))) {
+            hi = c;
+            break;
+        }
+        l = c;
+    }
+    const uint64_t he = first_h_gt(v, H, l + 1, hi);
+    const uint64_t hm = first_x_geq(v, make_ulonglong2(H.x | 1ull, H.y), hs, he);
+    const uint64_t na = hm - hs, nbb = he - hm, d = b - hs;
+    // merge path: i = number of A strings among the first d merged
+    uint64_t ilo = d > nbb ? d - nbb : 0, ihi = d < na ? d : na;
+    while (ilo < ihi) {
+        const uint64_t mid = ilo + (ihi - ilo) / 2;
+        if (k_le(v.z(hs + mid), v.z(hm + d - 1 - mid))) ilo = mid + 1;
+        else ihi = mid;
+    }
+    const uint64_t i = ilo;
+    uint64_t k = d - i;
+    if (i > 0 && k < nbb && k_eq(v.z(hs + i - 1), v.z(hm + k))) k += 1;  // keep the pair together
+    return {hs + i, hm + k, hm, he};
+}
+
+__global__ __launch_bounds__(kThreads) void k_rx_partition(const Ctrl* __restrict__ ctrl, int in_buf,
+                                                           const ulonglong2* __restrict__ X,
+                                                           const ulonglong2* __restrict__ Z, uint64_t cap,
+                                                           TileDesc* __restrict__ desc) {
+    if (ctrl->err) return;
+    const uint64_t nf = ctrl->nf[in_buf], n = nf + ctrl->nb[in_buf];
+    const uint64_t ntiles = (n + kRxTile - 1) / kRxTile;
+    const VIn v{X, Z, nf, cap};
+    for (uint64_t t = blockIdx.x * uint64_t(blockDim.x) + threadIdx.x; t <= ntiles;
+         t += uint64_t(gridDim.x) * blockDim.x) {
+        const uint64_t b = t * kRxTile;
+        desc[t] = rx_split(v, n, b < n ? b : n);
+    }
+}
+
+// ================================================================ RX: merge
+template <typename CT, int LP>
+__device__ __forceinline__ bool keep_row(const CT* c, const double* thr) {
+    bool keep = false;
+#pragma unroll
+    for (int a = 0; a < LP; ++a) keep |= absd(c[a]) > thr[a];
+    return keep;
+}
+
+template <typename CT, int LP>
+__global__ __launch_bounds__(kThreads) void k_rx_merge(RxArgs A, GateTrig g) {
+    __shared__ ulonglong2 sX[kRxTileMax];
+    __shared__ ulonglong2 sZ[kRxTileMax];
+    __shared__ uint16_t sStart[kRxTileMax + 2];
+    __shared__ uint16_t sMidx[kRxTileMax];
+    __shared__ uint8_t sAlive[kRxTileMax];
+    __shared__ uint32_t sWave[4];
+    __shared__ uint32_t sTile;
+    __shared__ uint64_t sBase[2];
+    __shared__ double sThr[LP];
+
+    Ctrl* ctrl = A.ctrl;
+    const CT* __restrict__ Cin = static_cast<const CT*>(A.Cin);
+    CT* __restrict__ Cout = static_cast<CT*>(A.Cout);
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6;
+    const bool skip = ctrl->err != 0u;
+    const uint64_t nf = ctrl->nf[A.in_buf];
+    const uint64_t n = nf + ctrl->nb[A.in_buf];
+    const uint64_t ntiles = skip ? 0 : (n + kRxTile - 1) / kRxTile;
+    const uint32_t ep = ctrl->epoch;
+    const bool filt = A.eps_in > 0.0;
+    if (tid < LP) sThr[tid] = filt ? A.eps_in * bits_to_d(ctrl->maxbits[A.mx_in][tid]) : -1.0;
+    double vmax[LP];
+#pragma unroll
+    for (int a = 0; a < LP; ++a) vmax[a] = 0.0;
+    __syncthreads();
+
+    for (;;) {
+        const uint32_t tile = acquire_tile(ctrl, &sTile);
+        if (tile >= ntiles) break;
+        const TileDesc d0 = A.desc[tile], d1 = A.desc[tile + 1];
+        const bool same = (d0.hm == d1.hm) && (d0.he == d1.he);
+        const uint64_t r1s = d0.posA, r1e = same ? d1.posA : d0.hm;
+        const uint64_t r2s = d0.posB, r2e = same ? d1.posB : d1.posA;
+        const uint64_t r3s = same ? 0 : d1.hm, r3e = same ? 0 : d1.posB;
+        const bool sane = r1s <= r1e && r2s <= r2e && r3s <= r3e && r1e <= n && r2e <= n && r3e <= n &&
+                          (r1e - r1s) + (r2e - r2s) + (r3e - r3s) <= kRxTileMax;
+        if (!sane && tid == 0) atomicOr(&ctrl->err, kErrInternal);
+        const uint32_t l1 = sane ? uint32_t(r1e - r1s) : 0u, l2 = sane ? uint32_t(r2e - r2s) : 0u,
+                       l3 = sane ? uint32_t(r3e - r3s) : 0u;
+        const uint32_t m = l1 + l2 + l3;  // <= kRxTileMax by construction
+        auto logical = [&](uint32_t e) -> uint64_t {
+            return e < l1 ? r1s + e : (e < l1 + l2 ? r2s + (e - l1) : r3s + (e - l1 - l2));
+        };
+
+        // ---- load keys (input order) and the pending-truncation flags
+        for (uint32_t e = tid; e < m; e += kThreads) {
+            const uint64_t p = vphys(logical(e), nf, A.cap);
+            sX[e] = A.Xin[p];
+            sZ[e] = A.Zin[p];
+            sAlive[e] = filt ? uint8_t(keep_row<CT, LP>(Cin + p * LP, sThr)) : uint8_t(1);
+        }
+        __syncthreads();
+
+        // ---- x-groups ("parts"): ids and starts
+        const uint32_t e0 = tid * kRxIPT;
+        uint32_t flags = 0, cnt = 0;
+#pragma unroll
+        for (int k = 0; k < kRxIPT; ++k) {
+            const uint32_t e = e0 + k;
+            const bool f = e < m && (e == 0 || !k_eq(sX[e], sX[e - 1]));
+            flags |= uint32_t(f) << k;
+            cnt += f;
+        }
+        uint32_t npart;
+        uint32_t pid = block_excl_scan(cnt, sWave, npart);
+#pragma unroll
+        for (int k = 0; k < kRxIPT; ++k) {
+            if (flags >> k & 1u) sStart[pid++] = uint16_t(e0 + k);
+        }
+        if (tid == 0) {
+            sStart[npart] = uint16_t(m);
+            sStart[npart + 1] = uint16_t(m);
+        }
+        for (uint32_t e = tid; e < m; e += kThreads) sMidx[e] = 0;
+        __syncthreads();
+
+        // ---- merged position of every string
+        {
+            uint32_t p = pid - __popc(flags);  // part id of element e0 minus 1 if e0 starts a part
+#pragma unroll
+            for (int k = 0; k < kRxIPT; ++k) {
+                const uint32_t e = e0 + k;
+                if (e >= m) break;
+                if (flags >> k & 1u) ++p;
+                const uint32_t mypart = p - 1;  // id of e's part
+                const ulonglong2 xe = sX[e], ze = sZ[e];
+                uint32_t os = 0, oe = 0;
+                uint32_t mpos;
+                if ((xe.x & 1ull) == 0) {
+                    if (mypart + 1 < npart) {
+                        const uint32_t s = sStart[mypart + 1];
+                        if (sX[s].x == (xe.x | 1ull) && sX[s].y == xe.y) {
+                            os = s;
+                            oe = sStart[mypart + 2];
+                        }
+                    }
+                    uint32_t lo = os, hi = oe;  // count of partner-group z < ze
+                    while (lo < hi) {
+                        const uint32_t mid = (lo + hi) >> 1;
+                        if (k_lt(sZ[mid], ze)) lo = mid + 1;
+                        else hi = mid;
+                    }
+                    mpos = e + (lo - os);
+                } else {
+                    const uint32_t ps = sStart[mypart];
+                    if (mypart >= 1) {
+                        const uint32_t s = sStart[mypart - 1];
+                        if (sX[s].x == (xe.x & ~1ull) && sX[s].y == xe.y) {
+                            os = s;
+                            oe = ps;
+                        }
+                    }
+                    uint32_t lo = os, hi = oe;  // count of partner-group z <= ze
+                    while (lo < hi) {
+                        const uint32_t mid = (lo + hi) >> 1;
+                        if (k_le(sZ[mid], ze)) lo = mid + 1;
+                        else hi = mid;
+                    }
+                    mpos = e - (oe - os) + (lo - os);
+                }
+                if (mpos < m) sMidx[mpos] = uint16_t(e);
+                else atomicOr(&ctrl->err, kErrInternal);
+            }
+        }
+        __syncthreads();
+
+        // ---- emission plan in merged order
+        const int zw = g.zword;
+        const uint64_t zmask = 1ull << g.zbit;
+        uint32_t plan = 0;  // per k: bit 4k emitA, 4k+1 emitB, 4k+2 live pair owner
+        uint32_t cntA = 0, cntB = 0;
+#pragma unroll
+        for (int k = 0; k < kRxIPT; ++k) {
+            const uint32_t q = e0 + k;
+            if (q >= m) break;
+            const uint32_t e = sMidx[q];
+            if (!sAlive[e]) continue;
+            const ulonglong2 xe = sX[e], ze = sZ[e];
+            const bool isB = xe.x & 1ull;
+            const bool ac = ((zw == 0 ? ze.x : ze.y) & zmask) != 0ull;
+            bool eA, eB, pair = false;
+            if (!isB) {
+                bool partner = false;
+                if (q + 1 < m) {
+                    const uint32_t e2 = sMidx[q + 1];
+                    partner = sX[e2].x == (xe.x | 1ull) && sX[e2].y == xe.y && k_eq(sZ[e2], ze) && sAlive[e2];
+                }
+                if (partner) {
+                    eA = eB = pair = true;
+                } else if (ac) {
+                    eA = g.any_c;
+                    eB = g.any_s;
+                } else {
+                    eA = true;
+                    eB = false;
+                }
+            } else {
+                bool partner = false;
+                if (q > 0) {
+                    const uint32_t e1 = sMidx[q - 1];
+                    partner = sX[e1].x == (xe.x & ~1ull) && sX[e1].y == xe.y && k_eq(sZ[e1], ze) && sAlive[e1];
+                }
+                if (partner) {
+                    eA = eB = false;  // handled by the A string of the pair
+                } else if (ac) {
+                    eA = g.any_s;
+                    eB = g.any_c;
+                } else {
+                    eA = false;
+                    eB = true;
+                }
+            }
+            plan |= (uint32_t(eA) | (uint32_t(eB) << 1) | (uint32_t(pair) << 2)) << (4 * k);
+            cntA += eA;
+            cntB += eB;
+        }
+        uint32_t totPacked;
+        const uint32_t offPacked = block_excl_scan(cntA | (cntB << 16), sWave, totPacked);
+        const uint32_t totA = totPacked & 0xFFFFu, totB = totPacked >> 16;
+
+        // ---- tile bases: wave 0 front run, wave 1 back run
+        if (wave == 0) {
+            const uint64_t b = lookback_wave(A.status, 1, tile, ep, totA, &ctrl->err);
+            if (lane_id() == 0) sBase[0] = b;
+        } else if (wave == 1) {
+            const uint64_t b = lookback_wave(A.status + A.max_tiles, 1, tile, ep, totB, &ctrl->err);
+            if (lane_id() == 0) sBase[1] = b;
+        }
+        __syncthreads();
+        const uint64_t baseA = sBase[0], baseB = sBase[1];
+        if (tile == ntiles - 1 && tid == 0) {
+            const uint64_t tf = baseA + totA, tb = baseB + totB;
+            if (tf + tb > A.cap) {
+                atomicOr(&ctrl->err, kErrCapacity);
+                atomicMax(reinterpret_cast<unsigned long long*>(&ctrl->need),
+                          static_cast<unsigned long long>(tf + tb));
+            } else {
+                ctrl->nf[A.out_buf] = tf;
+                ctrl->nb[A.out_buf] = tb;
+            }
+        }
+
+        // ---- compute and write outputs
+        uint64_t oA = baseA + (offPacked & 0xFFFFu), oB = baseB + (offPacked >> 16);
+#pragma unroll
+        for (int k = 0; k < kRxIPT; ++k) {
+            const uint32_t pl = (plan >> (4 * k)) & 0xFu;
+            if (!(pl & 3u)) continue;
+            const uint32_t q = e0 + k;
+            const uint32_t e = sMidx[q];
+            const ulonglong2 xe = sX[e], ze = sZ[e];
+            const bool isB = xe.x & 1ull;
+            const bool ac = ((zw == 0 ? ze.x : ze.y) & zmask) != 0ull;
+            const CT* ce = Cin + vphys(logical(e), nf, A.cap) * LP;
+            const bool eA = pl & 1u, eB = pl & 2u, pair = pl & 4u;
+            CT vA[LP], vB[LP];
+            if (pair) {
+                const CT* cb = Cin + vphys(logical(sMidx[q + 1]), nf, A.cap) * LP;
+#pragma unroll
+                for (int a = 0; a < LP; ++a) {
+                    const CT ca = ce[a], cbv = cb[a];
+                    if (ac) {
+                        // A receives the child of its Y partner (sign -), B that of its Z partner (+)
+                        vA[a] = Arith<CT>::pair(g, a, ca, cbv, true);
+                        vB[a] = Arith<CT>::pair(g, a, cbv, ca, false);
+                    } else {
+                        vA[a] = ca;
+                        vB[a] = cbv;
+                    }
+                }
+            } else if (!isB) {
+#pragma unroll
+                for (int a = 0; a < LP; ++a) {
+                    const CT ca = ce[a];
+                    vA[a] = ac ? Arith<CT>::scale_c(g, a, ca) : ca;
+                    vB[a] = Arith<CT>::scale_s(g, a, ca, false);
+                }
+            } else {
+#pragma unroll
+                for (int a = 0; a < LP; ++a) {
+                    const CT cbv = ce[a];
+                    vB[a] = ac ? Arith<CT>::scale_c(g, a, cbv) : cbv;
+                    vA[a] = Arith<CT>::scale_s(g, a, cbv, true);
+                }
+            }
+            const ulonglong2 xa = rotr1_n(make_ulonglong2(xe.x & ~1ull, xe.y), A.nq);
+            const ulonglong2 xb = rotr1_n(make_ulonglong2(xe.x | 1ull, xe.y), A.nq);
+            if (eA) {
+                if (oA < A.cap) {
+                    A.Xout[oA] = xa;
+                    A.Zout[oA] = ze;
+                    CT* dst = Cout + oA * LP;
+#pragma unroll
+                    for (int a = 0; a < LP; ++a) {
+                        dst[a] = vA[a];
+                        vmax[a] = fmax(vmax[a], absd(vA[a]));
+                    }
+                }
+                ++oA;
+            }
+            if (eB) {
+                if (oB < A.cap) {
+                    const uint64_t p = A.cap - 1 - oB;
+                    A.Xout[p] = xb;
+                    A.Zout[p] = ze;
+                    CT* dst = Cout + p * LP;
+#pragma unroll
+                    for (int a = 0; a < LP; ++a) {
+                        dst[a] = vB[a];
+                        vmax[a] = fmax(vmax[a], absd(vB[a]));
+                    }
+                }
+                ++oB;
+            }
+        }
+        __syncthreads();
+    }
+
+    // ---- per-lane max of the outputs
+#pragma unroll
+    for (int a = 0; a < LP; ++a) {
+        const double mx = wave_max_d(vmax[a]);
+        if (lane_id() == 0 && mx > 0.0)
+            atomicMax(reinterpret_cast<unsigned long long*>(&ctrl->maxbits[A.mx_out][a]),
+                      static_cast<unsigned long long>(d_to_bits(mx)));
+    }
+    if (finish_launch(ctrl)) {
+        // a failed stage keeps its input (and the input's max) for the re-run
+        if (__hip_atomic_load(&ctrl->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u) {
+            for (int a = 0; a < kMaxLanes; ++a) ctrl->maxbits[A.mx_in][a] = 0ull;
+            if (ntiles == 0) {
+                ctrl->nf[A.out_buf] = 0;
+                ctrl->nb[A.out_buf] = 0;
+            }
+            ctrl->stages_done += 1;
+            ctrl->cnt_updates += n;
+            ctrl->cnt_rx_in += n;
+            ctrl->cnt_rx_out += ctrl->nf[A.out_buf] + ctrl->nb[A.out_buf];
+            ctrl->cnt_rx_launches += 1;
+        }
+    }
+}
+
+// ================================================================ Clifford pass / compaction
+// Reads the virtual input array, applies the pending truncation, then (if
+// ngens > 0) every Z-only Clifford generator in order (each a signed
+// permutation of strings: x unchanged, z ^= z_J, coefficient times
+// sign(B(K,J)) * sin(theta) when the string anticommutes), and writes the
+// survivors compacted to the front of the output.  rank_out (optional)
+// receives the index of each string's x-group, the major key of the re-sort.
+
+__device__ __forceinline__ bool child_sign_negative_z(const ulonglong2& x, const ulonglong2& zI,
+                                                      const ulonglong2& zK) {
+    // sigma_K sigma_J = i^e sigma_I with x_J = 0:
+    // e = |x & z_K| - |x & z_I| (mod 4); the child factor is +1 for e = 3, -1 for e = 1.
+    const int e = k_popc_and(x, zK) - k_popc_and(x, zI);
+    return (e & 3) == 1;
+}
+
+template <typename CT, int LP>
+__global__ __launch_bounds__(kThreads) void k_compact(CompactArgs A) {
+    __shared__ CliffGen sG[kMaxCliffGens];
+    __shared__ uint32_t sWave[4];
+    __shared__ uint32_t sTile;
+    __shared__ uint64_t sBase[2];
+    __shared__ double sThr[LP];
+
+    Ctrl* ctrl = A.ctrl;
+    const CT* __restrict__ Cin = static_cast<const CT*>(A.Cin);
+    CT* __restrict__ Cout = static_cast<CT*>(A.Cout);
+    const int tid = threadIdx.x, wave = tid >> 6;
+    const bool skip = ctrl->err != 0u;
+    const uint64_t nf = ctrl->nf[A.in_buf];
+    const uint64_t n = nf + ctrl->nb[A.in_buf];
+    const uint64_t ntiles = skip ? 0 : (n + kCompactTile - 1) / kCompactTile;
+    const uint32_t ep = ctrl->epoch;
+    const bool filt = A.eps_in > 0.0;
+    if (tid < LP) sThr[tid] = filt ? A.eps_in * bits_to_d(ctrl->maxbits[A.mx_in][tid]) : -1.0;
+    for (int i = tid; i < A.ngens; i += kThreads) sG[i] = A.gens[i];
+    double vmax[LP];
+#pragma unroll
+    for (int a = 0; a < LP; ++a) vmax[a] = 0.0;
+    __syncthreads();
+
+    for (;;) {
+        const uint32_t tile = acquire_tile(ctrl, &sTile);
+        if (tile >= ntiles) break;
+        const uint64_t t0 = uint64_t(tile) * kCompactTile;
+        ulonglong2 xs[kCompactIPT], zs[kCompactIPT];
+        CT cs[kCompactIPT][LP];
+        uint32_t alive = 0, gst = 0, nal = 0, ngs = 0;
+#pragma unroll
+        for (int k = 0; k < kCompactIPT; ++k) {
+            const uint64_t i = t0 + uint64_t(tid) * kCompactIPT + k;
+            if (i >= n) break;
+            const uint64_t p = vphys(i, nf, A.cap);
+            xs[k] = A.Xin[p];
+            zs[k] = A.Zin[p];
+#pragma unroll
+            for (int a = 0; a < LP; ++a) cs[k][a] = Cin[p * LP + a];
+            bool al = true;
+            if (filt) al = keep_row<CT, LP>(cs[k], sThr);
+            bool gs = (i == 0);
+            if (!gs) {
+                const ulonglong2 xp = A.Xin[vphys(i - 1, nf, A.cap)];
+                gs = !k_eq(xp, xs[k]);
+            }
+            alive |= uint32_t(al) << k;
+            gst |= uint32_t(gs) << k;
+            nal += al;
+            ngs += gs;
+        }
+        uint32_t totPacked;
+        const uint32_t offPacked = block_excl_scan(nal | (ngs << 16), sWave, totPacked);
+        if (wave == 0) {
+            const uint64_t b = lookback_wave(A.status, 1, tile, ep, totPacked & 0xFFFFu, &ctrl->err);
+            if (lane_id() == 0) sBase[0] = b;
+        } else if (wave == 1) {
+            const uint64_t b = lookback_wave(A.status + A.max_tiles, 1, tile, ep, totPacked >> 16, &ctrl->err);
+            if (lane_id() == 0) sBase[1] = b;
+        }
+        __syncthreads();
+        uint64_t o = sBase[0] + (offPacked & 0xFFFFu);
+        uint64_t rk = sBase[1] + (offPacked >> 16);  // group starts before this thread's strings
+        if (tile == ntiles - 1 && tid == 0) {
+            ctrl->nf[A.out_buf] = sBase[0] + (totPacked & 0xFFFFu);
+            ctrl->nb[A.out_buf] = 0;
+            ctrl->nranks = sBase[1] + (totPacked >> 16);
+        }
+#pragma unroll
+        for (int k = 0; k < kCompactIPT; ++k) {
+            rk += (gst >> k) & 1u;
+            if (!((alive >> k) & 1u)) continue;
+            ulonglong2 z = zs[k];
+            bool neg = false;
+            if (A.ngens > 0) {
+                const ulonglong2 x = rotl_n(xs[k], A.xrot, A.nq);
+                for (int gi = 0; gi < A.ngens; ++gi) {
+                    const CliffGen G = sG[gi];
+                    const int par = (__popcll(x.x & G.z0) + __popcll(x.y & G.z1)) & 1;
+                    if (!par) continue;
+                    if (G.kodd) {
+                        const ulonglong2 zk = make_ulonglong2(z.x ^ G.z0, z.y ^ G.z1);
+                        neg ^= child_sign_negative_z(x, z, zk) ^ (G.neg != 0u);
+                        z = zk;
+                    } else {
+                        neg ^= (G.neg != 0u);
+                    }
+                }
+            }
+            A.Xout[o] = xs[k];
+            A.Zout[o] = z;
+            if (A.rank_out) A.rank_out[o] = uint32_t(rk - 1);
+#pragma unroll
+            for (int a = 0; a < LP; ++a) {
+                const CT v = neg ? -cs[k][a] : cs[k][a];
+                Cout[o * LP + a] = v;
+                vmax[a] = fmax(vmax[a], absd(v));
+            }
+            ++o;
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int a = 0; a < LP; ++a) {
+        const double mx = wave_max_d(vmax[a]);
+        if (lane_id() == 0 && mx > 0.0)
+            atomicMax(reinterpret_cast<unsigned long long*>(&ctrl->maxbits[A.mx_out][a]),
+                      static_cast<unsigned long long>(d_to_bits(mx)));
+    }
+    if (finish_launch(ctrl)) {
+        if (__hip_atomic_load(&ctrl->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u) {
+            for (int a = 0; a < kMaxLanes; ++a) ctrl->maxbits[A.mx_in][a] = 0ull;
+            if (ntiles == 0) {
+                ctrl->nf[A.out_buf] = 0;
+                ctrl->nb[A.out_buf] = 0;
+                ctrl->nranks = 0;
+            }
+            ctrl->stages_done += 1;
+            ctrl->cnt_updates += n * uint64_t(A.gate_count);
+            ctrl->cnt_cliff_in += n;
+            ctrl->cnt_cliff_launches += 1;
+        }
+    }
+}
+
+// ================================================================ onesweep radix sort
+// Key = (rank, z1, z0) compared as an unsigned integer; LSD by 8-bit digits,
+// one stable pass per digit with decoupled look-back across tiles for the
+// 256 bucket offsets (Adinets & Merrill, "Onesweep", 2022).
+
+__device__ __forceinline__ uint32_t sort_digit(int digit, uint32_t r, const ulonglong2& z) {
+    if (digit < 8) return uint32_t(z.x >> (8 * digit)) & 0xFFu;
+    if (digit < 16) return uint32_t(z.y >> (8 * (digit - 8))) & 0xFFu;
+    return (r >> (8 * (digit - 16))) & 0xFFu;
+}
+
+__global__ __launch_bounds__(kThreads) void k_sort_hist(const Ctrl* __restrict__ ctrl, int buf,
+                                                        const uint32_t* __restrict__ R,
+                                                        const ulonglong2* __restrict__ Z,
+                                                        uint32_t* __restrict__ hist) {
+    __shared__ uint32_t sh[kSortDigits][256];
+    for (int i = threadIdx.x; i < kSortDigits * 256; i += kThreads) (&sh[0][0])[i] = 0;
+    __syncthreads();
+    const uint64_t n = ctrl->nf[buf];
+    if (!ctrl->err) {
+        for (uint64_t i = blockIdx.x * uint64_t(kThreads) + threadIdx.x; i < n; i += uint64_t(gridDim.x) * kThreads) {
+            const ulonglong2 z = Z[i];
+            const uint32_t r = R[i];
+#pragma unroll
+            for (int d = 0; d < kSortDigits; ++d) atomicAdd(&sh[d][sort_digit(d, r, z)], 1u);
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < kSortDigits * 256; i += kThreads) {
+        const uint32_t v = (&sh[0][0])[i];
+        if (v) atomicAdd(hist + i, v);
+    }
+}
+
+template <typename CT, int LP>
+__global__ __launch_bounds__(kThreads) void k_sort_pass(SortPassArgs A) {
+    __shared__ uint32_t sCnt[4][256];
+    __shared__ uint64_t sOff[4][256];
+    __shared__ uint32_t sTile;
+    Ctrl* ctrl = A.ctrl;
+    const CT* __restrict__ Cs = static_cast<const CT*>(A.Cs);
+    CT* __restrict__ Cd = static_cast<CT*>(A.Cd);
+    const int tid = threadIdx.x, wave = tid >> 6, lane = lane_id();
+    const bool skip = ctrl->err != 0u;
+    const uint64_t ntiles = skip ? 0 : (A.n + kSortTile - 1) / kSortTile;
+    const uint32_t ep = ctrl->epoch;
+    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+
+    for (;;) {
+        const uint32_t tile = acquire_tile(ctrl, &sTile);
+        if (tile >= ntiles) break;
+        for (int i = tid; i < 4 * 256; i += kThreads) (&sCnt[0][0])[i] = 0;
+        __syncthreads();
+        // warp-striped: wave w owns a contiguous segment of 64*IPT strings
+        const uint64_t seg = uint64_t(tile) * kSortTile + uint64_t(wave) * 64 * kSortIPT;
+        uint32_t dig[kSortIPT];
+        uint32_t loc[kSortIPT];
+#pragma unroll
+        for (int k = 0; k < kSortIPT; ++k) {
+            const uint64_t i = seg + uint64_t(k) * 64 + lane;
+            const bool valid = i < A.n;
+            uint32_t d = 0;
+            if (valid) d = sort_digit(A.digit, A.Rs[i], A.Zs[i]);
+            dig[k] = valid ? d : 0xFFFFFFFFu;
+            uint64_t peers = __ballot(valid);
+#pragma unroll
+            for (int b = 0; b < 8; ++b) {
+                const uint64_t bb = __ballot((d >> b) & 1u);
+                peers &= ((d >> b) & 1u) ? bb : ~bb;
+            }
+            uint32_t pre = 0;
+            if (valid) pre = sCnt[wave][d];
+            const uint32_t below = __popcll(peers & lt_mask);
+            loc[k] = pre + below;
+            if (valid && below == 0) sCnt[wave][d] = pre + __popcll(peers);
+        }
+        __syncthreads();
+        // per digit: prefix over waves, tile total, look-back across tiles
+        {
+            const int d = tid;
+            const uint32_t c0 = sCnt[0][d], c1 = sCnt[1][d], c2 = sCnt[2][d], c3 = sCnt[3][d];
+            const uint32_t tot = c0 + c1 + c2 + c3;
+            const uint64_t excl = lookback_thread(A.status + d, 256, tile, ep, tot, &ctrl->err);
+            const uint64_t b = uint64_t(A.digit_base[d]) + excl;
+            sOff[0][d] = b;
+            sOff[1][d] = b + c0;
+            sOff[2][d] = b + c0 + c1;
+            sOff[3][d] = b + c0 + c1 + c2;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < kSortIPT; ++k) {
+            if (dig[k] == 0xFFFFFFFFu) continue;
+            const uint64_t i = seg + uint64_t(k) * 64 + lane;
+            const uint64_t o = sOff[wave][dig[k]] + loc[k];
+            if (o >= A.n) continue;  // cannot happen for a consistent histogram
+            A.Rd[o] = A.Rs[i];
+            A.Zd[o] = A.Zs[i];
+            A.Xd[o] = A.Xs[i];
+#pragma unroll
+            for (int a = 0; a < LP; ++a) Cd[o * LP + a] = Cs[i * LP + a];
+        }
+        __syncthreads();
+    }
+    if (finish_launch(ctrl)) {
+        if (!skip) {
+            ctrl->nf[A.dst_buf] = A.n;
+            ctrl->nb[A.dst_buf] = 0;
+        }
+    }
+}
+
+// ================================================================ reductions
+// mode 0: <Z> = sum of c over the x == 0 prefix; mode 1: sum of c^2 over all.
+// Deterministic: fixed chunk per block, fixed tree, fixed final order.
+
+__global__ void k_prefix_len(Ctrl* ctrl, int buf, const ulonglong2* __restrict__ X, uint64_t cap) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const uint64_t nf = ctrl->nf[buf];
+    uint64_t lo = 0, hi = nf;  // x == 0 strings precede all others and sit in the front run
+    while (lo < hi) {
+        const uint64_t mid = lo + (hi - lo) / 2;
+        const ulonglong2 x = X[mid];
+        if (x.x == 0 && x.y == 0) lo = mid + 1;
+        else hi = mid;
+    }
+    ctrl->prefix_len = lo;
+}
+
+template <typename CT, int LP>
+__global__ __launch_bounds__(kThreads) void k_reduce_partial(const Ctrl* __restrict__ ctrl, int buf,
+                                                             const CT* __restrict__ C, uint64_t cap, int mode,
+                                                             double* __restrict__ partial) {
+    __shared__ double sAcc[4][LP];
+    const uint64_t nf = ctrl->nf[buf];
+    const uint64_t len = (mode == 0) ? ctrl->prefix_len : nf + ctrl->nb[buf];
+    const uint64_t chunk = (len + gridDim.x - 1) / gridDim.x;
+    const uint64_t b0 = blockIdx.x * chunk;
+    const uint64_t b1 = (b0 + chunk < len) ? b0 + chunk : len;
+    double acc[LP];
+#pragma unroll
+    for (int a = 0; a < LP; ++a) acc[a] = 0.0;
+    for (uint64_t i = b0 + threadIdx.x; i < b1; i += kThreads) {
+        const uint64_t p = vphys(i, nf, cap);
+#pragma unroll
+        for (int a = 0; a < LP; ++a) {
+            const double v = static_cast<double>(C[p * LP + a]);
+            acc[a] += (mode == 0) ? v : v * v;
+        }
+    }
+    const int wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int a = 0; a < LP; ++a) {
+        double v = acc[a];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+        if (lane_id() == 0) sAcc[wave][a] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < LP) {
+        const int a = threadIdx.x;
+        partial[blockIdx.x * LP + a] = ((sAcc[0][a] + sAcc[1][a]) + sAcc[2][a]) + sAcc[3][a];
+    }
+}
+
+template <int LP>
+__global__ void k_reduce_final(const double* __restrict__ partial, int nblocks, double* __restrict__ out) {
+    if (threadIdx.x < LP) {
+        const int a = threadIdx.x;
+        double s = 0.0;
+        for (int b = 0; b < nblocks; ++b) s += partial[b * LP + a];
+        out[a] = s;
+    }
+}
+
+__global__ void k_fill_u64(uint64_t* p, uint64_t v, size_t n) {
+    for (size_t i = blockIdx.x * size_t(blockDim.x) + threadIdx.x; i < n; i += size_t(gridDim.x) * blockDim.x)
+        p[i] = v;
+}
+
+// ================================================================ launchers
+
+#define ORQA_DISPATCH(DTYPE, LP, F)                      \
+    do {                                                 \
+        if ((DTYPE) == 0) {                              \
+            switch (LP) {                                \
+                case 1: F(double, 1); break;             \
+                case 2: F(double, 2); break;             \
+                case 4: F(double, 4); break;             \
+                case 8: F(double, 8); break;             \
+                case 16: F(double, 16); break;           \
+                case 32: F(double, 32); break;           \
+                default: return hipErrorInvalidValue;    \
+            }                                            \
+        } else {                                         \
+            switch (LP) {                                \
+                case 1: F(float, 1); break;              \
+                case 2: F(float, 2); break;              \
+                case 4: F(float, 4); break;              \
+                case 8: F(float, 8); break;              \
+                case 16: F(float, 16); break;            \
+                case 32: F(float, 32); break;            \
+                default: return hipErrorInvalidValue;    \
+            }                                            \
+        }                                                \
+    } while (0)
+
+hipError_t launch_rx_partition(const RxArgs& a, hipStream_t s) {
+    k_rx_partition<<<dim3(256), dim3(kThreads), 0, s>>>(a.ctrl, a.in_buf, a.Xin, a.Zin, a.cap, a.desc);
+    return hipGetLastError();
+}
+
+hipError_t launch_rx(const RxArgs& a, const GateTrig& g, int dtype, int lp, hipStream_t s, int grid) {
+#define L_RX(T, L) k_rx_merge<T, L><<<dim3(grid), dim3(kThreads), 0, s>>>(a, g)
+    ORQA_DISPATCH(dtype, lp, L_RX);
+#undef L_RX
+    return hipGetLastError();
+}
+
+hipError_t launch_compact(const CompactArgs& a, int dtype, int lp, hipStream_t s, int grid) {
+#define L_CP(T, L) k_compact<T, L><<<dim3(grid), dim3(kThreads), 0, s>>>(a)
+    ORQA_DISPATCH(dtype, lp, L_CP);
+#undef L_CP
+    return hipGetLastError();
+}
+
+hipError_t launch_sort_hist(Ctrl* ctrl, int buf, const uint32_t* R, const ulonglong2* Z, uint32_t* hist,
+                            hipStream_t s, int grid) {
+    k_sort_hist<<<dim3(grid), dim3(kThreads), 0, s>>>(ctrl, buf, R, Z, hist);
+    return hipGetLastError();
+}
+
+hipError_t launch_sort_pass(const SortPassArgs& a, int dtype, int lp, hipStream_t s, int grid) {
+#define L_SP(T, L) k_sort_pass<T, L><<<dim3(grid), dim3(kThreads), 0, s>>>(a)
+    ORQA_DISPATCH(dtype, lp, L_SP);
+#undef L_SP
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce(Ctrl* ctrl, int buf, const ulonglong2* X, const void* C, uint64_t cap, int mode,
+                         double* partial, double* out, int dtype, int lp, int lanes, hipStream_t s) {
+    (void)lanes;
+    if (mode == 0) k_prefix_len<<<1, 64, 0, s>>>(ctrl, buf, X, cap);
+#define L_RD(T, L)                                                                                    \
+    k_reduce_partial<T, L><<<dim3(kReduceBlocks), dim3(kThreads), 0, s>>>(ctrl, buf, static_cast<const T*>(C), \
+                                                                          cap, mode, partial);        \
+    k_reduce_final<L><<<1, 64, 0, s>>>(partial, kReduceBlocks, out)
+    ORQA_DISPATCH(dtype, lp, L_RD);
+#undef L_RD
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u64(uint64_t* p, uint64_t v, size_t n, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    k_fill_u64<<<dim3(256), dim3(256), 0, s>>>(p, v, n);
+    return hipGetLastError();
+}
+
+}  // namespace orqa
