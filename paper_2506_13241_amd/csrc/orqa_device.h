@@ -123,7 +123,7 @@ __device__ __forceinline__ uint32_t st_flag(uint64_t s, uint32_t ep) {
 // exclusive prefix of `tile` (uniform).  Publishes the aggregate first, so a
 // tile never waits before its own aggregate is visible: every wait ends once
 // the earlier tiles (which took their indices first) publish theirs.
-__device__ uint64_t lookback_wave(uint64_t* st, uint64_t stride, uint32_t tile, uint32_t ep, uint64_t agg,
+__device__ __forceinline__ uint64_t lookback_wave(uint64_t* st, uint64_t stride, uint32_t tile, uint32_t ep, uint64_t agg,
                                   uint32_t* err) {
     const int lane = lane_id();
     if (tile == 0) {
@@ -172,7 +172,7 @@ __device__ uint64_t lookback_wave(uint64_t* st, uint64_t stride, uint32_t tile, 
 
 // Single-thread look-back (one channel per thread, used by the radix sort with
 // one thread per digit).
-__device__ uint64_t lookback_thread(uint64_t* st, uint64_t stride, uint32_t tile, uint32_t ep, uint64_t agg,
+__device__ __forceinline__ uint64_t lookback_thread(uint64_t* st, uint64_t stride, uint32_t tile, uint32_t ep, uint64_t agg,
                                     uint32_t* err) {
     if (tile == 0) {
         st_rel(st, st_pack(ep, 2, agg));

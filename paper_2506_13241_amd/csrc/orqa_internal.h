@@ -19,9 +19,9 @@ constexpr uint32_t kErrInternal = 4u;  // inconsistent tile split (never expecte
 // boundary adjustment can move either end by one, so a tile holds at most
 // kRxTile + 1 <= kRxTileMax strings.
 constexpr int kThreads = 256;
-constexpr int kRxIPT = 4;
-constexpr int kRxTileMax = kThreads * kRxIPT;  // 1024
-constexpr int kRxTile = kRxTileMax - 2;        // 1022
+constexpr int kRxIPT = 3;
+constexpr int kRxTileMax = kThreads * kRxIPT;  // 768
+constexpr int kRxTile = kRxTileMax - 2;        // 766
 constexpr int kCompactIPT = 4;
 constexpr int kCompactTile = kThreads * kCompactIPT;  // 1024
 constexpr int kSortIPT = 8;

@@ -129,13 +129,57 @@ __device__ __forceinline__ bool keep_row(const CT* c, const double* thr) {
     return keep;
 }
 
+
+// Input ranges of one RX tile (uniform across the workgroup).
+struct RxTile {
+    uint64_t r1s, r2s, r3s;
+    uint32_t l1, l2, l3, m;
+    bool sane;
+};
+
+__device__ __forceinline__ RxTile rx_tile(const TileDesc* desc, uint32_t tile, uint64_t n) {
+    const TileDesc d0 = desc[tile], d1 = desc[tile + 1];
+    const bool same = (d0.hm == d1.hm) && (d0.he == d1.he);
+    const uint64_t r1s = d0.posA, r1e = same ? d1.posA : d0.hm;
+    const uint64_t r2s = d0.posB, r2e = same ? d1.posB : d1.posA;
+    const uint64_t r3s = same ? 0 : d1.hm, r3e = same ? 0 : d1.posB;
+    RxTile t;
+    t.sane = r1s <= r1e && r2s <= r2e && r3s <= r3e && r1e <= n && r2e <= n && r3e <= n &&
+             (r1e - r1s) + (r2e - r2s) + (r3e - r3s) <= uint64_t(kRxTileMax);
+    t.r1s = r1s;
+    t.r2s = r2s;
+    t.r3s = r3s;
+    t.l1 = t.sane ? uint32_t(r1e - r1s) : 0u;
+    t.l2 = t.sane ? uint32_t(r2e - r2s) : 0u;
+    t.l3 = t.sane ? uint32_t(r3e - r3s) : 0u;
+    t.m = t.l1 + t.l2 + t.l3;
+    return t;
+}
+
+__device__ __forceinline__ uint64_t rx_phys(const RxTile& t, uint32_t e, uint64_t nf, uint64_t cap) {
+    const uint64_t li = e < t.l1 ? t.r1s + e : (e < t.l1 + t.l2 ? t.r2s + (e - t.l1) : t.r3s + (e - t.l1 - t.l2));
+    return vphys(li, nf, cap);
+}
+
+// Output entry of an RX tile: source string e, partner e2 and kind.
+//   kind 0: copy c_e; 1: cos * c_e; 2: child sin * c_e (sign by side);
+//   kind 3: pair cos * c_e + sin * c_e2 (sign by side)
+// Front side (x_j = 0 after the gate) takes the child of a Y partner with the
+// minus sign, the back side the child of a Z partner with the plus sign.
+__device__ __forceinline__ uint32_t out_entry(uint32_t e, uint32_t e2, uint32_t kind) {
+    return e | (e2 << 10) | (kind << 20);
+}
+
 template <typename CT, int LP>
 __global__ __launch_bounds__(kThreads) void k_rx_merge(RxArgs A, GateTrig g) {
+    constexpr bool kStageC = LP * sizeof(CT) <= 8;  // coefficients staged in LDS
     __shared__ ulonglong2 sX[kRxTileMax];
     __shared__ ulonglong2 sZ[kRxTileMax];
+    __shared__ CT sC[kStageC ? kRxTileMax * LP : 1];
     __shared__ uint16_t sStart[kRxTileMax + 2];
     __shared__ uint16_t sMidx[kRxTileMax];
     __shared__ uint8_t sAlive[kRxTileMax];
+    __shared__ uint32_t sOut[2][kRxTileMax];
     __shared__ uint32_t sWave[4];
     __shared__ uint32_t sTile;
     __shared__ uint64_t sBase[2];
@@ -157,35 +201,61 @@ __global__ __launch_bounds__(kThreads) void k_rx_merge(RxArgs A, GateTrig g) {
 #pragma unroll
     for (int a = 0; a < LP; ++a) vmax[a] = 0.0;
     __syncthreads();
+    const int zw = g.zword;
+    const uint64_t zmask = 1ull << g.zbit;
+    const uint64_t cap = A.cap;
 
     for (;;) {
         const uint32_t tile = acquire_tile(ctrl, &sTile);
         if (tile >= ntiles) break;
-        const TileDesc d0 = A.desc[tile], d1 = A.desc[tile + 1];
-        const bool same = (d0.hm == d1.hm) && (d0.he == d1.he);
-        const uint64_t r1s = d0.posA, r1e = same ? d1.posA : d0.hm;
-        const uint64_t r2s = d0.posB, r2e = same ? d1.posB : d1.posA;
-        const uint64_t r3s = same ? 0 : d1.hm, r3e = same ? 0 : d1.posB;
-        const bool sane = r1s <= r1e && r2s <= r2e && r3s <= r3e && r1e <= n && r2e <= n && r3e <= n &&
-                          (r1e - r1s) + (r2e - r2s) + (r3e - r3s) <= kRxTileMax;
-        if (!sane && tid == 0) atomicOr(&ctrl->err, kErrInternal);
-        const uint32_t l1 = sane ? uint32_t(r1e - r1s) : 0u, l2 = sane ? uint32_t(r2e - r2s) : 0u,
-                       l3 = sane ? uint32_t(r3e - r3s) : 0u;
-        const uint32_t m = l1 + l2 + l3;  // <= kRxTileMax by construction
-        auto logical = [&](uint32_t e) -> uint64_t {
-            return e < l1 ? r1s + e : (e < l1 + l2 ? r2s + (e - l1) : r3s + (e - l1 - l2));
-        };
+        const RxTile T = rx_tile(A.desc, tile, n);
+        if (!T.sane && tid == 0) atomicOr(&ctrl->err, kErrInternal);
+        const uint32_t m = T.m;
 
-        // ---- load keys (input order) and the pending-truncation flags
-        for (uint32_t e = tid; e < m; e += kThreads) {
-            const uint64_t p = vphys(logical(e), nf, A.cap);
-            sX[e] = A.Xin[p];
-            sZ[e] = A.Zin[p];
-            sAlive[e] = filt ? uint8_t(keep_row<CT, LP>(Cin + p * LP, sThr)) : uint8_t(1);
+        // ---- keys (and coefficients) of the tile into LDS.  Every slot loads
+        // (slots past the tile end re-read string 0 of the tile), so the values
+        // stay in registers and all loads are in flight together.
+        if (m > 0) {
+            uint64_t rxl[kRxIPT], rxh[kRxIPT], rzl[kRxIPT], rzh[kRxIPT];
+            CT rc[kRxIPT][kStageC ? LP : 1];
+#pragma unroll
+            for (int k = 0; k < kRxIPT; ++k) {
+                const uint32_t e = k * kThreads + tid;
+                const uint64_t p = rx_phys(T, e < m ? e : 0u, nf, cap);
+                const ulonglong2 x = A.Xin[p], z = A.Zin[p];
+                rxl[k] = x.x;
+                rxh[k] = x.y;
+                rzl[k] = z.x;
+                rzh[k] = z.y;
+                if constexpr (kStageC) {
+#pragma unroll
+                    for (int a = 0; a < LP; ++a) rc[k][a] = Cin[p * LP + a];
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < kRxIPT; ++k) {
+                const uint32_t e = k * kThreads + tid;
+                if (e < m) {
+                    sX[e] = make_ulonglong2(rxl[k], rxh[k]);
+                    sZ[e] = make_ulonglong2(rzl[k], rzh[k]);
+                    if constexpr (kStageC) {
+                        bool keep = !filt;
+#pragma unroll
+                        for (int a = 0; a < LP; ++a) {
+                            sC[e * LP + a] = rc[k][a];
+                            keep |= absd(rc[k][a]) > sThr[a];
+                        }
+                        sAlive[e] = uint8_t(keep);
+                    } else {
+                        sAlive[e] =
+                            filt ? uint8_t(keep_row<CT, LP>(Cin + rx_phys(T, e, nf, cap) * LP, sThr)) : uint8_t(1);
+                    }
+                }
+            }
         }
         __syncthreads();
 
-        // ---- x-groups ("parts"): ids and starts
+        // ---- x-groups ("parts"): ids and starts (blocked: thread owns e0..e0+IPT-1)
         const uint32_t e0 = tid * kRxIPT;
         uint32_t flags = 0, cnt = 0;
 #pragma unroll
@@ -197,29 +267,28 @@ __global__ __launch_bounds__(kThreads) void k_rx_merge(RxArgs A, GateTrig g) {
         }
         uint32_t npart;
         uint32_t pid = block_excl_scan(cnt, sWave, npart);
+        const uint32_t pid0 = pid;
 #pragma unroll
         for (int k = 0; k < kRxIPT; ++k) {
-            if (flags >> k & 1u) sStart[pid++] = uint16_t(e0 + k);
+            if ((flags >> k) & 1u) sStart[pid++] = uint16_t(e0 + k);
         }
         if (tid == 0) {
             sStart[npart] = uint16_t(m);
             sStart[npart + 1] = uint16_t(m);
         }
-        for (uint32_t e = tid; e < m; e += kThreads) sMidx[e] = 0;
         __syncthreads();
 
-        // ---- merged position of every string
+        // ---- merged position of every string (merge by z of the two x-groups of a block)
         {
-            uint32_t p = pid - __popc(flags);  // part id of element e0 minus 1 if e0 starts a part
+            uint32_t p = pid0;
 #pragma unroll
             for (int k = 0; k < kRxIPT; ++k) {
                 const uint32_t e = e0 + k;
-                if (e >= m) break;
-                if (flags >> k & 1u) ++p;
-                const uint32_t mypart = p - 1;  // id of e's part
+                if (e >= m) continue;
+                if ((flags >> k) & 1u) ++p;
+                const uint32_t mypart = p - 1;
                 const ulonglong2 xe = sX[e], ze = sZ[e];
-                uint32_t os = 0, oe = 0;
-                uint32_t mpos;
+                uint32_t os = 0, oe = 0, mpos;
                 if ((xe.x & 1ull) == 0) {
                     if (mypart + 1 < npart) {
                         const uint32_t s = sStart[mypart + 1];
@@ -228,7 +297,7 @@ __global__ __launch_bounds__(kThreads) void k_rx_merge(RxArgs A, GateTrig g) {
                             oe = sStart[mypart + 2];
                         }
                     }
-                    uint32_t lo = os, hi = oe;  // count of partner-group z < ze
+                    uint32_t lo = os, hi = oe;  // partner-group strings with z < ze
                     while (lo < hi) {
                         const uint32_t mid = (lo + hi) >> 1;
                         if (k_lt(sZ[mid], ze)) lo = mid + 1;
@@ -244,7 +313,7 @@ __global__ __launch_bounds__(kThreads) void k_rx_merge(RxArgs A, GateTrig g) {
                             oe = ps;
                         }
                     }
-                    uint32_t lo = os, hi = oe;  // count of partner-group z <= ze
+                    uint32_t lo = os, hi = oe;  // partner-group strings with z <= ze
                     while (lo < hi) {
                         const uint32_t mid = (lo + hi) >> 1;
                         if (k_le(sZ[mid], ze)) lo = mid + 1;
@@ -259,58 +328,62 @@ __global__ __launch_bounds__(kThreads) void k_rx_merge(RxArgs A, GateTrig g) {
         __syncthreads();
 
         // ---- emission plan in merged order
-        const int zw = g.zword;
-        const uint64_t zmask = 1ull << g.zbit;
-        uint32_t plan = 0;  // per k: bit 4k emitA, 4k+1 emitB, 4k+2 live pair owner
+        uint32_t entA[kRxIPT], entB[kRxIPT];
         uint32_t cntA = 0, cntB = 0;
 #pragma unroll
         for (int k = 0; k < kRxIPT; ++k) {
+            entA[k] = entB[k] = 0xFFFFFFFFu;
             const uint32_t q = e0 + k;
-            if (q >= m) break;
+            if (q >= m) continue;
             const uint32_t e = sMidx[q];
             if (!sAlive[e]) continue;
             const ulonglong2 xe = sX[e], ze = sZ[e];
             const bool isB = xe.x & 1ull;
             const bool ac = ((zw == 0 ? ze.x : ze.y) & zmask) != 0ull;
-            bool eA, eB, pair = false;
             if (!isB) {
-                bool partner = false;
+                uint32_t e2 = 0xFFFFu;
                 if (q + 1 < m) {
-                    const uint32_t e2 = sMidx[q + 1];
-                    partner = sX[e2].x == (xe.x | 1ull) && sX[e2].y == xe.y && k_eq(sZ[e2], ze) && sAlive[e2];
+                    const uint32_t c = sMidx[q + 1];
+                    if (sX[c].x == (xe.x | 1ull) && sX[c].y == xe.y && k_eq(sZ[c], ze) && sAlive[c]) e2 = c;
                 }
-                if (partner) {
-                    eA = eB = pair = true;
+                if (e2 != 0xFFFFu) {
+                    entA[k] = out_entry(e, e2, ac ? 3u : 0u);
+                    entB[k] = out_entry(e2, e, ac ? 3u : 0u);
                 } else if (ac) {
-                    eA = g.any_c;
-                    eB = g.any_s;
+                    if (g.any_c) entA[k] = out_entry(e, 0, 1u);
+                    if (g.any_s) entB[k] = out_entry(e, 0, 2u);
                 } else {
-                    eA = true;
-                    eB = false;
+                    entA[k] = out_entry(e, 0, 0u);
                 }
             } else {
-                bool partner = false;
+                bool paired = false;
                 if (q > 0) {
-                    const uint32_t e1 = sMidx[q - 1];
-                    partner = sX[e1].x == (xe.x & ~1ull) && sX[e1].y == xe.y && k_eq(sZ[e1], ze) && sAlive[e1];
+                    const uint32_t c = sMidx[q - 1];
+                    paired = sX[c].x == (xe.x & ~1ull) && sX[c].y == xe.y && k_eq(sZ[c], ze) && sAlive[c];
                 }
-                if (partner) {
-                    eA = eB = false;  // handled by the A string of the pair
+                if (paired) {
+                    // emitted by the A string of the pair
                 } else if (ac) {
-                    eA = g.any_s;
-                    eB = g.any_c;
+                    if (g.any_s) entA[k] = out_entry(e, 0, 2u);
+                    if (g.any_c) entB[k] = out_entry(e, 0, 1u);
                 } else {
-                    eA = false;
-                    eB = true;
+                    entB[k] = out_entry(e, 0, 0u);
                 }
             }
-            plan |= (uint32_t(eA) | (uint32_t(eB) << 1) | (uint32_t(pair) << 2)) << (4 * k);
-            cntA += eA;
-            cntB += eB;
+            cntA += entA[k] != 0xFFFFFFFFu;
+            cntB += entB[k] != 0xFFFFFFFFu;
         }
         uint32_t totPacked;
         const uint32_t offPacked = block_excl_scan(cntA | (cntB << 16), sWave, totPacked);
         const uint32_t totA = totPacked & 0xFFFFu, totB = totPacked >> 16;
+        {
+            uint32_t oa = offPacked & 0xFFFFu, ob = offPacked >> 16;
+#pragma unroll
+            for (int k = 0; k < kRxIPT; ++k) {
+                if (entA[k] != 0xFFFFFFFFu) sOut[0][oa++] = entA[k];
+                if (entB[k] != 0xFFFFFFFFu) sOut[1][ob++] = entB[k];
+            }
+        }
 
         // ---- tile bases: wave 0 front run, wave 1 back run
         if (wave == 0) {
@@ -324,7 +397,7 @@ __global__ __launch_bounds__(kThreads) void k_rx_merge(RxArgs A, GateTrig g) {
         const uint64_t baseA = sBase[0], baseB = sBase[1];
         if (tile == ntiles - 1 && tid == 0) {
             const uint64_t tf = baseA + totA, tb = baseB + totB;
-            if (tf + tb > A.cap) {
+            if (tf + tb > cap) {
                 atomicOr(&ctrl->err, kErrCapacity);
                 atomicMax(reinterpret_cast<unsigned long long*>(&ctrl->need),
                           static_cast<unsigned long long>(tf + tb));
@@ -334,77 +407,35 @@ __global__ __launch_bounds__(kThreads) void k_rx_merge(RxArgs A, GateTrig g) {
             }
         }
 
-        // ---- compute and write outputs
-        uint64_t oA = baseA + (offPacked & 0xFFFFu), oB = baseB + (offPacked >> 16);
-#pragma unroll
-        for (int k = 0; k < kRxIPT; ++k) {
-            const uint32_t pl = (plan >> (4 * k)) & 0xFu;
-            if (!(pl & 3u)) continue;
-            const uint32_t q = e0 + k;
-            const uint32_t e = sMidx[q];
-            const ulonglong2 xe = sX[e], ze = sZ[e];
-            const bool isB = xe.x & 1ull;
-            const bool ac = ((zw == 0 ? ze.x : ze.y) & zmask) != 0ull;
-            const CT* ce = Cin + vphys(logical(e), nf, A.cap) * LP;
-            const bool eA = pl & 1u, eB = pl & 2u, pair = pl & 4u;
-            CT vA[LP], vB[LP];
-            if (pair) {
-                const CT* cb = Cin + vphys(logical(sMidx[q + 1]), nf, A.cap) * LP;
-#pragma unroll
-                for (int a = 0; a < LP; ++a) {
-                    const CT ca = ce[a], cbv = cb[a];
-                    if (ac) {
-                        // A receives the child of its Y partner (sign -), B that of its Z partner (+)
-                        vA[a] = Arith<CT>::pair(g, a, ca, cbv, true);
-                        vB[a] = Arith<CT>::pair(g, a, cbv, ca, false);
-                    } else {
-                        vA[a] = ca;
-                        vB[a] = cbv;
-                    }
-                }
-            } else if (!isB) {
+        // ---- coalesced writes of the front and back runs
+#pragma unroll 1
+        for (int side = 0; side < 2; ++side) {
+            const uint32_t tot = side ? totB : totA;
+            const uint64_t base = side ? baseB : baseA;
+            for (uint32_t i = tid; i < tot; i += kThreads) {
+                const uint32_t en = sOut[side][i];
+                const uint32_t e = en & 0x3FFu, e2 = (en >> 10) & 0x3FFu, kind = en >> 20;
+                const ulonglong2 xe = sX[e];
+                const ulonglong2 xo = rotr1_n(make_ulonglong2(side ? (xe.x | 1ull) : (xe.x & ~1ull), xe.y), A.nq);
+                const uint64_t o = base + i;
+                if (o >= cap) continue;
+                const uint64_t po = side ? cap - 1 - o : o;
+                A.Xout[po] = xo;
+                A.Zout[po] = sZ[e];
+                const bool neg = side == 0;
+                CT* dst = Cout + po * LP;
+                const CT* ce = kStageC ? (sC + e * LP) : (Cin + rx_phys(T, e, nf, cap) * LP);
+                const CT* ce2 = kStageC ? (sC + e2 * LP) : (Cin + rx_phys(T, e2, nf, cap) * LP);
 #pragma unroll
                 for (int a = 0; a < LP; ++a) {
-                    const CT ca = ce[a];
-                    vA[a] = ac ? Arith<CT>::scale_c(g, a, ca) : ca;
-                    vB[a] = Arith<CT>::scale_s(g, a, ca, false);
+                    CT v;
+                    if (kind == 0) v = ce[a];
+                    else if (kind == 1) v = Arith<CT>::scale_c(g, a, ce[a]);
+                    else if (kind == 2) v = Arith<CT>::scale_s(g, a, ce[a], neg);
+                    else v = Arith<CT>::pair(g, a, ce[a], ce2[a], neg);
+                    dst[a] = v;
+                    vmax[a] = fmax(vmax[a], absd(v));
                 }
-            } else {
-#pragma unroll
-                for (int a = 0; a < LP; ++a) {
-                    const CT cbv = ce[a];
-                    vB[a] = ac ? Arith<CT>::scale_c(g, a, cbv) : cbv;
-                    vA[a] = Arith<CT>::scale_s(g, a, cbv, true);
-                }
-            }
-            const ulonglong2 xa = rotr1_n(make_ulonglong2(xe.x & ~1ull, xe.y), A.nq);
-            const ulonglong2 xb = rotr1_n(make_ulonglong2(xe.x | 1ull, xe.y), A.nq);
-            if (eA) {
-                if (oA < A.cap) {
-                    A.Xout[oA] = xa;
-                    A.Zout[oA] = ze;
-                    CT* dst = Cout + oA * LP;
-#pragma unroll
-                    for (int a = 0; a < LP; ++a) {
-                        dst[a] = vA[a];
-                        vmax[a] = fmax(vmax[a], absd(vA[a]));
-                    }
-                }
-                ++oA;
-            }
-            if (eB) {
-                if (oB < A.cap) {
-                    const uint64_t p = A.cap - 1 - oB;
-                    A.Xout[p] = xb;
-                    A.Zout[p] = ze;
-                    CT* dst = Cout + p * LP;
-#pragma unroll
-                    for (int a = 0; a < LP; ++a) {
-                        dst[a] = vB[a];
-                        vmax[a] = fmax(vmax[a], absd(vB[a]));
-                    }
-                }
-                ++oB;
             }
         }
         __syncthreads();
