@@ -36,6 +36,24 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def measured_traffic():
+    """HBM bytes per RX merge launch from the committed rocprofv3 summary, or
+    None when the kernel source changed since those counters were taken."""
+    import glob
+    import hashlib
+    src = os.path.join(ROOT, "paper_2506_13241_amd", "csrc", "orqa_kernels.hip")
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "k_rx_merge__*fp64.md"))):
+        fields = {}
+        for line in open(path):
+            if ":" in line and not line.startswith(("#", " ", "|", "-")):
+                k, v = line.split(":", 1)
+                fields[k.strip()] = v.strip()
+        if fields.get("kernel_source_sha256_16") == sha and "traffic_bytes_per_launch" in fields:
+            return float(fields["traffic_bytes_per_launch"]), os.path.basename(path)
+    return None, None
+
+
 def cpu_baseline(theta, eps0, budget_s):
     """The FP64 std::map oracle, single-threaded, on a bounded sample of the
     same workload: Trotter steps 1.. from the start, gate by gate, until the
@@ -154,10 +172,15 @@ def main():
         "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 4),
         "traffic": None,
+        "traffic_source": None,
         "launches": int(st["rx_launches"]),
         "mean_launch_ms": round(rx_ms_mean, 4),
         "algorithmic_bytes_per_launch": round(rx_bytes / max(st["rx_launches"], 1)),
     }
+    traffic, tsrc = measured_traffic()
+    if traffic is not None:
+        roofline["traffic"] = traffic
+        roofline["traffic_source"] = tsrc
     extra = {
         "strings_before": n_before,
         "strings_after": n_after,
