@@ -99,9 +99,9 @@ int pauli_sum_destroy(ps_handle* h);
  *            lane a (max over the whole operator after that gate).  rel_eps <= 0
  *            keeps every generated string, exact zeros included.
  *   trunc_mode  PS_TRUNC_MAGNITUDE (rule above), PS_TRUNC_NONE (rel_eps
- *            ignored), PS_TRUNC_LEARNED (rule above with |O_I| scaled by the
- *            loaded scorer's estimate of the string's future weight, see
- *            pauli_sum_load_scorer).
+ *            ignored), PS_TRUNC_LEARNED (rule above after every gate, plus
+ *            the learned rule, see ps_scorer_create, once per run of Clifford
+ *            gates, i.e. once per Trotter step; needs a loaded scorer).
  * Fast paths: runs of Clifford gates whose generators hold only Z letters
  * (e.g. RZZ(-pi/2) layers) are fused into one pass plus one re-sort; sigma_x
  * rotations on consecutive qubits q, q+1, ... (each layer ascending, starting at
@@ -142,14 +142,47 @@ int pauli_sum_norm2(ps_handle* h, double* out);
 int pauli_sum_export(ps_handle* h, ps_pauli* keys, void* coeffs, size_t cap, size_t* n);
 
 /*
- * pauli_sum_load_scorer -- load the weights of the learned truncation scorer
- * (an MLP 160->128->128->1 with GELU, bf16 weights, fp32 accumulation) used by
- * PS_TRUNC_LEARNED.  bf16_w holds W1 (128x160), W2 (128x128), W3 (1x128), row
- * major, n_w = 37376; f32_b holds b1 (128), b2 (128), b3 (1), n_b = 257.
- * obs_qubit is the qubit the observable sits on (distance features).
+ * Learned truncation scorer (PS_TRUNC_LEARNED).  A small network (160 -> 128
+ * -> 128 -> 1, GELU, bf16 weights, fp32 accumulation) maps a string's key to
+ * y = log10 of the predicted weight g_I with which the string still reaches
+ * <Z> after the rest of the circuit; learned truncation drops strings with
+ * |O_I,a| * min(1, 10^y) <= rel_eps * max_I |O_I,a| in every lane.  The paper
+ * uses the magnitude rule (Eq. truncation1) and names tailored truncation as
+ * future work (Conclusion; Appendix D); this is that extension, with the
+ * magnitude rule kept as its fallback.
+ *
+ * Features: feature f counts the qubits of qmask[f] (two words) that carry
+ * letter letters[f] (0 X, 1 Y, 2 Z, 3 any non-identity), times scales[f].
+ * Parameters: one fp32 vector of 37249 values, W1 (128x160 row major), b1
+ * (128), W2 (128x128), b2 (128), W3 (128), b3 (1).
+ *
+ * ps_scorer_create      allocate a scorer for n_qubits with the 160 feature
+ *                       definitions (host arrays: qmask 320 words, letters
+ *                       160, scales 160); parameters start at zero.
+ * ps_scorer_set_params  upload parameters (resets the Adam moments).
+ * ps_scorer_get_params  download parameters.
+ * ps_scorer_set_data    upload a training set: n keys and n fp32 targets.
+ * ps_scorer_forward     network outputs y (host out[n], may be NULL) and the
+ *                       bf16 features (host out[n*160], may be NULL) of the
+ *                       training set.
+ * ps_scorer_loss_grad   mean squared error of y against the targets and its
+ *                       gradient (host out[37249], may be NULL).
+ * ps_scorer_adam_step   one Adam step (beta 0.9/0.999, eps 1e-8) with the
+ *                       last gradient.
+ * pauli_sum_load_scorer copy the scorer's network into the handle (the scorer
+ *                       may be destroyed afterwards).
  */
-int pauli_sum_load_scorer(ps_handle* h, const uint16_t* bf16_w, size_t n_w,
-                          const float* f32_b, size_t n_b, int obs_qubit);
+typedef struct ps_scorer ps_scorer;
+int ps_scorer_create(int n_qubits, const uint64_t* qmask, const uint8_t* letters, const float* scales,
+                     void* hip_stream, ps_scorer** out);
+int ps_scorer_destroy(ps_scorer* s);
+int ps_scorer_set_params(ps_scorer* s, const float* params, size_t n);
+int ps_scorer_get_params(ps_scorer* s, float* params, size_t n);
+int ps_scorer_set_data(ps_scorer* s, const ps_pauli* keys, const float* targets, size_t n);
+int ps_scorer_forward(ps_scorer* s, float* y, uint16_t* features);
+int ps_scorer_loss_grad(ps_scorer* s, double* loss, float* grad);
+int ps_scorer_adam_step(ps_scorer* s, float lr);
+int pauli_sum_load_scorer(ps_handle* h, const ps_scorer* s);
 
 /*
  * Counters and timing for measurement.  Counters accumulate since creation or

@@ -25,7 +25,10 @@ EXPORTED_SYMBOLS = (
     "pauli_sum_create", "pauli_sum_destroy", "apply_rotation_layer", "pauli_sum_gates_applied",
     "pauli_sum_truncate", "expectation_z", "pauli_sum_size", "pauli_sum_norm2", "pauli_sum_export",
     "pauli_sum_load_scorer", "pauli_sum_set_timing", "pauli_sum_stats", "ps_last_error",
+    "ps_scorer_create", "ps_scorer_destroy", "ps_scorer_set_params", "ps_scorer_get_params", "ps_scorer_set_data",
+    "ps_scorer_forward", "ps_scorer_loss_grad", "ps_scorer_adam_step",
 )
+N_SCORER_PARAMS = 37249
 
 
 class PsError(RuntimeError):
@@ -73,10 +76,18 @@ def load_library(path: str = LIB_PATH):
         "pauli_sum_size": (I, [P, ctypes.POINTER(S)]),
         "pauli_sum_norm2": (I, [P, P]),
         "pauli_sum_export": (I, [P, P, P, S, ctypes.POINTER(S)]),
-        "pauli_sum_load_scorer": (I, [P, P, S, P, S, I]),
+        "pauli_sum_load_scorer": (I, [P, P]),
         "pauli_sum_set_timing": (I, [P, I]),
         "pauli_sum_stats": (I, [P, ctypes.POINTER(ps_stats), I]),
         "ps_last_error": (ctypes.c_char_p, []),
+        "ps_scorer_create": (I, [I, P, P, P, P, ctypes.POINTER(P)]),
+        "ps_scorer_destroy": (I, [P]),
+        "ps_scorer_set_params": (I, [P, P, S]),
+        "ps_scorer_get_params": (I, [P, P, S]),
+        "ps_scorer_set_data": (I, [P, P, P, S]),
+        "ps_scorer_forward": (I, [P, P, P]),
+        "ps_scorer_loss_grad": (I, [P, ctypes.POINTER(D), P]),
+        "ps_scorer_adam_step": (I, [P, ctypes.c_float]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -196,6 +207,74 @@ class PauliSum:
         t, c = self.export()
         return {tuple(int(v) for v in row): c[i].copy() for i, row in enumerate(t)}
 
+    def load_scorer(self, scorer: "PsScorer"):
+        """Copy a scorer's network into this handle (for PS_TRUNC_LEARNED)."""
+        _check(_lib.pauli_sum_load_scorer(self._h, scorer._h))
+        return self
+
+
+class PsScorer:
+    """Learned truncation scorer: feature table, network and its training set
+    on the GPU (semantics in include/orqa.h).  The feature table comes from
+    paper_2506_13241_amd.scorer.feature_table."""
+
+    def __init__(self, n_qubits: int, qmask, letters, scales, stream=None):
+        lib = load_library()
+        qmask = np.ascontiguousarray(qmask, dtype=np.uint64).reshape(160, 2)
+        letters = np.ascontiguousarray(letters, dtype=np.uint8).reshape(160)
+        scales = np.ascontiguousarray(scales, dtype=np.float32).reshape(160)
+        self.n_qubits = n_qubits
+        self.n = 0
+        h = ctypes.c_void_p()
+        if stream is None:
+            stream = current_stream()
+        _check(lib.ps_scorer_create(n_qubits, _ptr(qmask), _ptr(letters), _ptr(scales), stream, ctypes.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and _lib is not None:
+            _lib.ps_scorer_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        self.close()
+
+    def set_params(self, params):
+        p = np.ascontiguousarray(params, dtype=np.float32).reshape(-1)
+        _check(_lib.ps_scorer_set_params(self._h, _ptr(p), p.size))
+        return self
+
+    def get_params(self) -> np.ndarray:
+        p = np.empty(N_SCORER_PARAMS, dtype=np.float32)
+        _check(_lib.ps_scorer_get_params(self._h, _ptr(p), p.size))
+        return p
+
+    def set_data(self, keys, targets):
+        k = _words_to_pauli(keys)
+        t = np.ascontiguousarray(targets, dtype=np.float32).reshape(-1)
+        if t.size != k.shape[0]:
+            raise ValueError("one target per key")
+        _check(_lib.ps_scorer_set_data(self._h, _ptr(k), _ptr(t), k.shape[0]))
+        self.n = k.shape[0]
+        return self
+
+    def forward(self, features: bool = False):
+        """Network outputs of the training set (and its bf16 features as uint16)."""
+        y = np.empty(self.n, dtype=np.float32)
+        f = np.empty((self.n, 160), dtype=np.uint16) if features else None
+        _check(_lib.ps_scorer_forward(self._h, _ptr(y), _ptr(f) if features else None))
+        return (y, f) if features else y
+
+    def loss_grad(self, grad: bool = True):
+        loss = ctypes.c_double()
+        g = np.empty(N_SCORER_PARAMS, dtype=np.float32) if grad else None
+        _check(_lib.ps_scorer_loss_grad(self._h, ctypes.byref(loss), _ptr(g) if grad else None))
+        return (loss.value, g) if grad else loss.value
+
+    def adam_step(self, lr: float):
+        _check(_lib.ps_scorer_adam_step(self._h, lr))
+        return self
+
 
 # C-ABI names at module level (same names, same meaning).
 def pauli_sum_create(n_qubits, terms, coeffs, dtype=PS_F64, capacity=0, stream=None) -> PauliSum:
@@ -231,3 +310,15 @@ def pauli_sum_norm2(ps: PauliSum):
 
 def pauli_sum_export(ps: PauliSum):
     return ps.export()
+
+
+def pauli_sum_load_scorer(ps: PauliSum, scorer: PsScorer):
+    return ps.load_scorer(scorer)
+
+
+def ps_scorer_create(n_qubits, qmask, letters, scales, stream=None) -> PsScorer:
+    return PsScorer(n_qubits, qmask, letters, scales, stream=stream)
+
+
+def ps_scorer_destroy(s: PsScorer):
+    s.close()

@@ -10,6 +10,7 @@
 
 #include "../../include/orqa.h"
 #include "orqa_internal.h"
+#include "orqa_scorer.h"
 
 using namespace orqa;
 
@@ -26,6 +27,26 @@ int fail(int code, const char* fmt, ...) {
     g_last_error = buf;
     return code;
 }
+
+}  // namespace
+
+namespace orqa {
+int api_fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+int scorer_alloc(ScorerDev* d);
+void scorer_free(ScorerDev* d);
+int scorer_copy(ScorerDev* dst, const ScorerDev* src, hipStream_t s);
+const ScorerDev* scorer_dev(const ps_scorer* s);
+}  // namespace orqa
+
+namespace {
 
 #define HIP_TRY(expr)                                                                          \
     do {                                                                                       \
@@ -116,6 +137,10 @@ struct ps_handle {
     size_t gates_applied = 0;
     uint64_t n_host = 0;  // size after the last synchronisation
     bool broken = false;
+    // learned truncation
+    bool has_scorer = false;
+    ScorerDev scorer{};
+    float* gscore = nullptr;  // cap floats
     // measurement: event pairs around launches, folded into host totals at syncs
     bool timing = false;
     std::vector<hipEvent_t> ev_pool;
@@ -129,55 +154,118 @@ namespace {
 
 size_t coef_bytes(const ps_handle* h) { return h->csize; }
 
-void free_buffers(ps_handle* h) {
-    for (int b = 0; b < 2; ++b) {
-        if (h->buf[b].X) (void)hipFree(h->buf[b].X);
-        if (h->buf[b].Z) (void)hipFree(h->buf[b].Z);
-        if (h->buf[b].C) (void)hipFree(h->buf[b].C);
-        if (h->rank[b]) (void)hipFree(h->rank[b]);
-        h->buf[b] = {};
-        h->rank[b] = nullptr;
+// Device memory of the handle comes in three parts so that growing never holds
+// more than the kept state buffer besides the new allocation: the two state
+// buffers (keys and coefficients, `cap` strings each) and the per-capacity
+// auxiliaries (rank arrays, tile descriptors, look-back status words, and the
+// learned-score array when a scorer is loaded).
+struct Aux {
+    uint32_t* rank[2] = {nullptr, nullptr};
+    TileDesc* desc = nullptr;
+    uint64_t* status = nullptr;
+    size_t status_words = 0;
+    uint64_t max_tiles = 0;
+    float* gscore = nullptr;
+};
+
+bool grab(void** p, size_t bytes) {
+    if (hipMalloc(p, bytes ? bytes : 16) != hipSuccess) {
+        (void)hipGetLastError();
+        *p = nullptr;
+        return false;
     }
-    if (h->desc) (void)hipFree(h->desc);
-    if (h->status) (void)hipFree(h->status);
-    h->desc = nullptr;
-    h->status = nullptr;
+    return true;
 }
 
-// Allocate both state buffers, the rank arrays and the per-tile scratch for
-// `cap` strings.  On failure nothing is leaked and PS_ERR_CAPACITY returned.
-int alloc_buffers(ps_handle* h, size_t cap, Buf out[2], uint32_t* rk[2], TileDesc** desc, uint64_t** status,
-                  size_t* status_words, uint64_t* max_tiles) {
-    std::vector<void*> got;
-    auto grab = [&](void** p, size_t bytes) -> bool {
-        if (hipMalloc(p, bytes ? bytes : 16) != hipSuccess) {
-            (void)hipGetLastError();
-            return false;
-        }
-        got.push_back(*p);
+void free_state(Buf* b) {
+    if (b->X) (void)hipFree(b->X);
+    if (b->Z) (void)hipFree(b->Z);
+    if (b->C) (void)hipFree(b->C);
+    *b = {};
+}
+
+bool alloc_state(ps_handle* h, size_t cap, Buf* b) {
+    *b = {};
+    if (grab(reinterpret_cast<void**>(&b->X), cap * sizeof(ulonglong2)) &&
+        grab(reinterpret_cast<void**>(&b->Z), cap * sizeof(ulonglong2)) && grab(&b->C, cap * coef_bytes(h)))
         return true;
-    };
-    bool ok = true;
-    for (int b = 0; b < 2 && ok; ++b) {
-        ok = grab(reinterpret_cast<void**>(&out[b].X), cap * sizeof(ulonglong2)) &&
-             grab(reinterpret_cast<void**>(&out[b].Z), cap * sizeof(ulonglong2)) &&
-             grab(&out[b].C, cap * coef_bytes(h)) && grab(reinterpret_cast<void**>(&rk[b]), cap * sizeof(uint32_t));
-    }
+    free_state(b);
+    return false;
+}
+
+void free_aux(Aux* a) {
+    void* ps[] = {a->rank[0], a->rank[1], a->desc, a->status, a->gscore};
+    for (void* p : ps)
+        if (p) (void)hipFree(p);
+    *a = Aux{};
+}
+
+bool alloc_aux(ps_handle* h, size_t cap, bool with_score, Aux* a) {
+    *a = Aux{};
     const uint64_t mt = cap / kRxTile + 4;
     const uint64_t st_tiles = cap / kCompactTile + 4;
     const uint64_t sort_tiles = cap / kSortTile + 4;
-    size_t words = std::max<size_t>(2 * std::max(mt, st_tiles), 256 * sort_tiles);
-    if (ok) ok = grab(reinterpret_cast<void**>(desc), (mt + 2) * sizeof(TileDesc));
-    if (ok) ok = grab(reinterpret_cast<void**>(status), words * sizeof(uint64_t));
+    const size_t words = std::max<size_t>(2 * std::max(mt, st_tiles), 256 * sort_tiles);
+    bool ok = grab(reinterpret_cast<void**>(&a->rank[0]), cap * sizeof(uint32_t)) &&
+              grab(reinterpret_cast<void**>(&a->rank[1]), cap * sizeof(uint32_t)) &&
+              grab(reinterpret_cast<void**>(&a->desc), (mt + 2) * sizeof(TileDesc)) &&
+              grab(reinterpret_cast<void**>(&a->status), words * sizeof(uint64_t));
+    if (ok && with_score) ok = grab(reinterpret_cast<void**>(&a->gscore), cap * sizeof(float));
+    // status words start from a zero epoch tag the kernels never use (epoch starts at 1)
+    if (ok) ok = hipMemsetAsync(a->status, 0, words * sizeof(uint64_t), h->stream) == hipSuccess;
     if (!ok) {
-        for (void* p : got) (void)hipFree(p);
+        free_aux(a);
+        return false;
+    }
+    a->status_words = words;
+    a->max_tiles = std::max(mt, st_tiles);
+    return true;
+}
+
+Aux take_aux(ps_handle* h) {
+    Aux a;
+    a.rank[0] = h->rank[0];
+    a.rank[1] = h->rank[1];
+    a.desc = h->desc;
+    a.status = h->status;
+    a.status_words = h->status_words;
+    a.max_tiles = h->max_tiles;
+    a.gscore = h->gscore;
+    h->rank[0] = h->rank[1] = nullptr;
+    h->desc = nullptr;
+    h->status = nullptr;
+    h->gscore = nullptr;
+    return a;
+}
+
+void put_aux(ps_handle* h, const Aux& a) {
+    h->rank[0] = a.rank[0];
+    h->rank[1] = a.rank[1];
+    h->desc = a.desc;
+    h->status = a.status;
+    h->status_words = a.status_words;
+    h->max_tiles = a.max_tiles;
+    h->gscore = a.gscore;
+}
+
+void free_buffers(ps_handle* h) {
+    free_state(&h->buf[0]);
+    free_state(&h->buf[1]);
+    Aux a = take_aux(h);
+    free_aux(&a);
+}
+
+// Allocate both state buffers and the auxiliaries for `cap` strings.  On
+// failure nothing is leaked and PS_ERR_CAPACITY is returned.
+int alloc_buffers(ps_handle* h, size_t cap) {
+    Aux a;
+    if (!alloc_state(h, cap, &h->buf[0]) || !alloc_state(h, cap, &h->buf[1]) ||
+        !alloc_aux(h, cap, h->has_scorer, &a)) {
+        free_state(&h->buf[0]);
+        free_state(&h->buf[1]);
         return fail(PS_ERR_CAPACITY, "hipMalloc failed for capacity %zu strings", cap);
     }
-    *status_words = words;
-    *max_tiles = std::max(mt, st_tiles);
-    // status words start from a zero epoch tag the kernels never use (epoch starts at 1)
-    if (hipMemsetAsync(*status, 0, words * sizeof(uint64_t), h->stream) != hipSuccess)
-        return fail(PS_ERR_HIP, "hipMemsetAsync(status) failed");
+    put_aux(h, a);
     return PS_OK;
 }
 
@@ -229,25 +317,49 @@ int ev_collect(ps_handle* h) {
 }
 
 // Grow capacity to at least `need`, keeping state buffer `keep` (front and back
-// runs) and its sizes; the other buffer's contents are discarded.
+// runs) and its sizes; the other buffer's contents are discarded.  Everything
+// but the kept buffer is released first, so the peak is the kept buffer plus
+// the new allocation.  If no larger capacity can be allocated the handle is
+// restored at its old capacity and PS_ERR_CAPACITY returned.
 int grow(ps_handle* h, int keep, uint64_t need) {
-    size_t ncap = std::max<size_t>(need + need / 4 + 1024, h->cap + h->cap / 2);
     Ctrl c;
     int rc = read_ctrl(h, &c);
     if (rc) return rc;
-    Buf nb[2] = {};
-    uint32_t* nr[2] = {nullptr, nullptr};
-    TileDesc* nd = nullptr;
-    uint64_t* ns = nullptr;
-    size_t nw = 0;
-    uint64_t nmt = 0;
-    rc = alloc_buffers(h, ncap, nb, nr, &nd, &ns, &nw, &nmt);
-    if (rc) {
-        // retry with the bare minimum
-        ncap = need + 1024;
-        if (ncap <= h->cap) return rc;
-        rc = alloc_buffers(h, ncap, nb, nr, &nd, &ns, &nw, &nmt);
-        if (rc) return rc;
+    free_state(&h->buf[1 - keep]);
+    {
+        Aux old = take_aux(h);
+        free_aux(&old);
+    }
+    const size_t want[3] = {std::max<size_t>(need + need / 4 + 1024, h->cap + h->cap / 2), need + 1024, h->cap};
+    size_t ncap = 0;
+    Buf nout{}, nkeep{};
+    Aux na;
+    for (size_t cap : want) {
+        if (cap < need && cap != h->cap) continue;
+        if (!alloc_state(h, cap, &nout)) continue;
+        if (!alloc_aux(h, cap, h->has_scorer, &na)) {
+            free_state(&nout);
+            continue;
+        }
+        if (cap != h->cap && !alloc_state(h, cap, &nkeep)) {
+            free_state(&nout);
+            free_aux(&na);
+            continue;
+        }
+        ncap = cap;
+        break;
+    }
+    if (ncap == 0) {
+        h->broken = true;
+        return fail(PS_ERR_CAPACITY, "hipMalloc failed while restoring capacity %zu (handle is no longer usable)",
+                    h->cap);
+    }
+    h->buf[1 - keep] = nout;
+    put_aux(h, na);
+    if (ncap == h->cap) {
+        HIP_TRY(hipStreamSynchronize(h->stream));
+        return fail(PS_ERR_CAPACITY, "hipMalloc failed for capacity %zu strings (kept capacity %zu)",
+                    size_t(need + need / 4 + 1024), h->cap);
     }
     const uint64_t f = c.nf[keep], b = c.nb[keep];
     const size_t cb = coef_bytes(h);
@@ -255,23 +367,16 @@ int grow(ps_handle* h, int keep, uint64_t need) {
         return bytes ? hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, h->stream) : hipSuccess;
     };
     const Buf& o = h->buf[keep];
-    Buf& d = nb[keep];
-    HIP_TRY(cpy(d.X, o.X, f * sizeof(ulonglong2)));
-    HIP_TRY(cpy(d.Z, o.Z, f * sizeof(ulonglong2)));
-    HIP_TRY(cpy(d.C, o.C, f * cb));
-    HIP_TRY(cpy(d.X + (ncap - b), o.X + (h->cap - b), b * sizeof(ulonglong2)));
-    HIP_TRY(cpy(d.Z + (ncap - b), o.Z + (h->cap - b), b * sizeof(ulonglong2)));
-    HIP_TRY(cpy(static_cast<char*>(d.C) + (ncap - b) * cb, static_cast<const char*>(o.C) + (h->cap - b) * cb, b * cb));
+    HIP_TRY(cpy(nkeep.X, o.X, f * sizeof(ulonglong2)));
+    HIP_TRY(cpy(nkeep.Z, o.Z, f * sizeof(ulonglong2)));
+    HIP_TRY(cpy(nkeep.C, o.C, f * cb));
+    HIP_TRY(cpy(nkeep.X + (ncap - b), o.X + (h->cap - b), b * sizeof(ulonglong2)));
+    HIP_TRY(cpy(nkeep.Z + (ncap - b), o.Z + (h->cap - b), b * sizeof(ulonglong2)));
+    HIP_TRY(cpy(static_cast<char*>(nkeep.C) + (ncap - b) * cb, static_cast<const char*>(o.C) + (h->cap - b) * cb,
+                b * cb));
     HIP_TRY(hipStreamSynchronize(h->stream));
-    free_buffers(h);
-    for (int i = 0; i < 2; ++i) {
-        h->buf[i] = nb[i];
-        h->rank[i] = nr[i];
-    }
-    h->desc = nd;
-    h->status = ns;
-    h->status_words = nw;
-    h->max_tiles = nmt;
+    free_state(&h->buf[keep]);
+    h->buf[keep] = nkeep;
     h->cap = ncap;
     return PS_OK;
 }
@@ -306,7 +411,26 @@ int check_no_error(ps_handle* h, const char* what) {
 // ---------------------------------------------------------------- stages
 
 int enqueue_compact(ps_handle* h, int in, int out, int mx_in, int mx_out, double eps_in, const CliffGen* gens,
-                    int ngens, bool with_rank, int gate_count = 0) {
+                    int ngens, bool with_rank, int gate_count = 0, double eps_learned = -1.0) {
+    const bool learned = eps_learned > 0.0;
+    if (learned) {  // score every input string, then the compaction applies the learned rule
+        ScorerFwdArgs f{};
+        f.net = h->scorer;
+        f.X = h->buf[in].X;
+        f.Z = h->buf[in].Z;
+        f.nf_ptr = &h->ctrl->nf[in];
+        f.nb_ptr = &h->ctrl->nb[in];
+        f.cap = h->cap;
+        f.xrot = h->xrot;
+        f.nq = h->nq;
+        f.y_out = h->gscore;
+        size_t slot;
+        int rc = ev_begin(h, 1, &slot);
+        if (rc) return rc;
+        HIP_TRY(launch_scorer_forward(f, h->stream, h->grid / 4));
+        rc = ev_end(h, slot);
+        if (rc) return rc;
+    }
     CompactArgs a{};
     a.ctrl = h->ctrl;
     a.in_buf = in;
@@ -329,6 +453,8 @@ int enqueue_compact(ps_handle* h, int in, int out, int mx_in, int mx_out, double
     a.gens = gens;
     a.ngens = ngens;
     a.gate_count = gate_count;
+    a.gscore = learned ? h->gscore : nullptr;
+    a.eps_learned = learned ? eps_learned : 0.0;
     size_t slot;
     int rc = ev_begin(h, 1, &slot);
     if (rc) return rc;
@@ -555,7 +681,7 @@ int pauli_sum_create(int n_qubits, int n_lanes, int dtype, size_t capacity, cons
         (void)hipGetLastError();
         return bail(fail(PS_ERR_CAPACITY, "hipMalloc failed for handle scratch"));
     }
-    rc = alloc_buffers(h, cap, h->buf, h->rank, &h->desc, &h->status, &h->status_words, &h->max_tiles);
+    rc = alloc_buffers(h, cap);
     if (rc) return bail(rc);
     Ctrl c;
     std::memset(&c, 0, sizeof c);
@@ -602,6 +728,7 @@ int pauli_sum_destroy(ps_handle* h) {
     if (h->red_out) (void)hipFree(h->red_out);
     if (h->cgens) (void)hipFree(h->cgens);
     for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
+    if (h->has_scorer) scorer_free(&h->scorer);
     delete h;
     return PS_OK;
 }
@@ -621,8 +748,10 @@ int apply_rotation_layer(ps_handle* h, const ps_pauli* gens, const double* theta
     if (!gens || !thetas) return fail(PS_ERR_INVALID, "gens/thetas NULL");
     if (trunc_mode != PS_TRUNC_NONE && trunc_mode != PS_TRUNC_MAGNITUDE && trunc_mode != PS_TRUNC_LEARNED)
         return fail(PS_ERR_INVALID, "unknown trunc_mode %d", trunc_mode);
-    if (trunc_mode == PS_TRUNC_LEARNED) return fail(PS_ERR_UNSUPPORTED, "learned truncation is not built in this library");
+    if (trunc_mode == PS_TRUNC_LEARNED && !h->has_scorer)
+        return fail(PS_ERR_INVALID, "PS_TRUNC_LEARNED needs pauli_sum_load_scorer first");
     if (std::isnan(rel_eps)) return fail(PS_ERR_NONFINITE, "rel_eps is NaN");
+    const double eps_learned = (trunc_mode == PS_TRUNC_LEARNED && rel_eps > 0.0) ? rel_eps : -1.0;
     const double eps = (trunc_mode == PS_TRUNC_NONE || !(rel_eps > 0.0)) ? -1.0 : rel_eps;
     for (size_t g = 0; g < n_gates; ++g) {
         if (!validate_key(h->nq, gens[g])) return fail(PS_ERR_INVALID, "generator %zu has bits above n_qubits", g);
@@ -749,7 +878,7 @@ int apply_rotation_layer(ps_handle* h, const ps_pauli* gens, const double* theta
         bool sort_after = false;
         for (; si < stages.size(); ++si) {
             Stage& s = stages[si];
-            const bool noop = s.kind == ST_CLIFF && s.gens.empty() && !(h->pend > 0.0);
+            const bool noop = s.kind == ST_CLIFF && s.gens.empty() && !(h->pend > 0.0) && !(eps_learned > 0.0);
             if (noop) {
                 // the gates leave every magnitude (and the max) unchanged:
                 // only the pending threshold of this layer is recorded
@@ -767,7 +896,7 @@ int apply_rotation_layer(ps_handle* h, const ps_pauli* gens, const double* theta
                     HIP_TRY(hipMemcpyAsync(h->cgens, s.gens.data(), s.gens.size() * sizeof(CliffGen),
                                            hipMemcpyHostToDevice, h->stream));
                 rc = enqueue_compact(h, in, out, mx_in, mx_out, h->pend, h->cgens, int(s.gens.size()),
-                                     s.needs_sort, int(s.gate_count));
+                                     s.needs_sort, int(s.gate_count), eps_learned);
                 if (rc) return rc;
                 if (!s.gens.empty()) HIP_TRY(hipStreamSynchronize(h->stream));  // cgens reused by the next run
             }
@@ -834,10 +963,19 @@ int apply_rotation_layer(ps_handle* h, const ps_pauli* gens, const double* theta
 int pauli_sum_truncate(ps_handle* h, double rel_eps, int trunc_mode) {
     if (!h) return fail(PS_ERR_INVALID, "handle is NULL");
     if (h->broken) return fail(PS_ERR_DEVICE, "handle is no longer usable");
-    if (trunc_mode == PS_TRUNC_LEARNED) return fail(PS_ERR_UNSUPPORTED, "learned truncation is not built in this library");
+    if (trunc_mode == PS_TRUNC_LEARNED && !h->has_scorer)
+        return fail(PS_ERR_INVALID, "PS_TRUNC_LEARNED needs pauli_sum_load_scorer first");
     int rc = materialize(h);
     if (rc) return rc;
     if (trunc_mode == PS_TRUNC_NONE || !(rel_eps > 0.0)) return PS_OK;
+    if (trunc_mode == PS_TRUNC_LEARNED) {
+        const int out = 1 - h->cur, mx_out = 1 - h->mx;
+        rc = enqueue_compact(h, h->cur, out, h->mx, mx_out, -1.0, nullptr, 0, false, 0, rel_eps);
+        if (rc) return rc;
+        h->cur = out;
+        h->mx = mx_out;
+        return check_no_error(h, "learned truncation");
+    }
     h->pend = rel_eps;
     return materialize(h);
 }
@@ -987,15 +1125,24 @@ int pauli_sum_stats(ps_handle* h, ps_stats* out, int reset) {
     return PS_OK;
 }
 
-int pauli_sum_load_scorer(ps_handle* h, const uint16_t* bf16_w, size_t n_w, const float* f32_b, size_t n_b,
-                          int obs_qubit) {
-    (void)bf16_w;
-    (void)n_w;
-    (void)f32_b;
-    (void)n_b;
-    (void)obs_qubit;
-    if (!h) return fail(PS_ERR_INVALID, "handle is NULL");
-    return fail(PS_ERR_UNSUPPORTED, "learned truncation is not built in this library");
+int pauli_sum_load_scorer(ps_handle* h, const ps_scorer* sc) {
+    if (!h || !sc) return fail(PS_ERR_INVALID, "NULL argument");
+    if (!h->has_scorer) {
+        int rc = scorer_alloc(&h->scorer);
+        if (rc) return rc;
+        h->has_scorer = true;
+    }
+    if (!h->gscore) {
+        if (hipMalloc(reinterpret_cast<void**>(&h->gscore), h->cap * sizeof(float)) != hipSuccess) {
+            (void)hipGetLastError();
+            h->gscore = nullptr;
+            return fail(PS_ERR_CAPACITY, "hipMalloc failed for the score array (%zu strings)", h->cap);
+        }
+    }
+    int rc = scorer_copy(&h->scorer, scorer_dev(sc), h->stream);
+    if (rc) return rc;
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    return PS_OK;
 }
 
 }  // extern "C"

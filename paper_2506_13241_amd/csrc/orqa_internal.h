@@ -95,8 +95,6 @@ struct RxArgs {
     uint64_t max_tiles;
     double eps_in;     // pending truncation of the input (<= 0: none)
     int nq;
-    // learned truncation (eps_in applies to |c| * g(features) when scorer != null)
-    const void* scorer;
 };
 
 struct CompactArgs {
@@ -117,7 +115,8 @@ struct CompactArgs {
     const CliffGen* gens;
     int ngens;
     int gate_count;      // gates this pass stands for (measurement counters)
-    const void* scorer;
+    const float* gscore;  // learned truncation: log10 predicted weight per input string, or null
+    double eps_learned;
 };
 
 struct SortPassArgs {

@@ -489,6 +489,7 @@ __global__ __launch_bounds__(kThreads) void k_compact(CompactArgs A) {
     __shared__ uint32_t sTile;
     __shared__ uint64_t sBase[2];
     __shared__ double sThr[LP];
+    __shared__ double sThrL[LP];
 
     Ctrl* ctrl = A.ctrl;
     const CT* __restrict__ Cin = static_cast<const CT*>(A.Cin);
@@ -500,7 +501,11 @@ __global__ __launch_bounds__(kThreads) void k_compact(CompactArgs A) {
     const uint64_t ntiles = skip ? 0 : (n + kCompactTile - 1) / kCompactTile;
     const uint32_t ep = ctrl->epoch;
     const bool filt = A.eps_in > 0.0;
-    if (tid < LP) sThr[tid] = filt ? A.eps_in * bits_to_d(ctrl->maxbits[A.mx_in][tid]) : -1.0;
+    if (tid < LP) {
+        const double M = bits_to_d(ctrl->maxbits[A.mx_in][tid]);
+        sThr[tid] = filt ? A.eps_in * M : -1.0;
+        sThrL[tid] = A.eps_learned * M;
+    }
     for (int i = tid; i < A.ngens; i += kThreads) sG[i] = A.gens[i];
     double vmax[LP];
 #pragma unroll
@@ -525,6 +530,13 @@ __global__ __launch_bounds__(kThreads) void k_compact(CompactArgs A) {
             for (int a = 0; a < LP; ++a) cs[k][a] = Cin[p * LP + a];
             bool al = true;
             if (filt) al = keep_row<CT, LP>(cs[k], sThr);
+            if (A.gscore) {  // learned rule: |c| * min(1, 10^y) > eps * M in some lane
+                const double gw = fmin(1.0, exp10(static_cast<double>(A.gscore[i])));
+                bool keepL = false;
+#pragma unroll
+                for (int a = 0; a < LP; ++a) keepL |= absd(cs[k][a]) * gw > sThrL[a];
+                al = al && keepL;
+            }
             bool gs = (i == 0);
             if (!gs) {
                 const ulonglong2 xp = A.Xin[vphys(i - 1, nf, A.cap)];

@@ -1,0 +1,325 @@
+// Learned truncation scorer on gfx950: string features, a 160-128-128-1 GELU
+// network with bf16 MFMA forward (fp32 accumulation), fp32 backward and Adam.
+//
+// The network estimates, from a string's key alone, the log10 of the weight
+// |g_I| with which the string will still reach <Z> after the remaining
+// circuit; truncation then keeps strings by |c_I| * g_I instead of |c_I|
+// (the paper leaves truncation schemes tailored to the problem as future work,
+// Conclusion and Appendix D).
+#include <algorithm>
+
+#include "orqa_scorer.h"
+
+namespace orqa {
+
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ uint16_t f2bf(float f) { return scorer_bf16(f); }  // round to nearest even
+__device__ __forceinline__ float bf2f(uint16_t b) { return __uint_as_float(static_cast<uint32_t>(b) << 16); }
+
+__device__ __forceinline__ float gelu(float x) { return 0.5f * x * (1.0f + erff(x * 0.70710678118654752f)); }
+__device__ __forceinline__ float gelu_grad(float x) {
+    const float cdf = 0.5f * (1.0f + erff(x * 0.70710678118654752f));
+    const float pdf = 0.3989422804014327f * expf(-0.5f * x * x);
+    return cdf + x * pdf;
+}
+
+// Feature f of a string: popcount of (letter mask of the string) & qmask[f],
+// times scale[f].  Letters: 0 X, 1 Y, 2 Z, 3 any non-identity.
+__device__ __forceinline__ float feature(const ulonglong2& mx, const ulonglong2& my, const ulonglong2& mz,
+                                         const ulonglong2& ma, const ulonglong2& q, uint32_t letter, float scale) {
+    const ulonglong2 m = letter == 0 ? mx : (letter == 1 ? my : (letter == 2 ? mz : ma));
+    return scale * static_cast<float>(__popcll(m.x & q.x) + __popcll(m.y & q.y));
+}
+
+// Shared memory of the forward kernel (one workgroup per CU).
+struct FwdLds {
+    alignas(16) uint16_t W1[kScH * kScIn];
+    alignas(16) uint16_t W2[kScH * kScH];
+    float W3[kScH];
+    float b1[kScH], b2[kScH], b3;
+    ulonglong2 qmask[kScIn];
+    float fscale[kScIn];
+    uint8_t letter[kScIn];
+    alignas(16) uint16_t F[kScTile * kScIn];  // features, later reused for h2
+    alignas(16) uint16_t H[kScTile * kScH];   // h1
+};
+
+// One 64x128 layer: D = A (64 x K, bf16 row-major in LDS) . W^T (W: 128 x K
+// bf16 row-major).  Wave w owns output column tiles 2w, 2w+1 for all four row
+// tiles.  mfma_f32_16x16x16 bf16 operand layout: lane l holds A[l%16][4(l/16)+i],
+// B[4(l/16)+i][l%16] and D[4(l/16)+i][l%16], i = 0..3.
+template <int K>
+__device__ __forceinline__ void layer64(const uint16_t* A, const uint16_t* W, floatx4 acc[4][2]) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int r = lane & 15, kq = (lane >> 4) * 4;
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[mt][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 2
+    for (int kt = 0; kt < K / 16; ++kt) {
+        bf16x4 b[2];
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int n = (2 * wave + j) * 16 + r;
+            b[j] = *reinterpret_cast<const bf16x4*>(W + n * K + kt * 16 + kq);
+        }
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) {
+            const bf16x4 a = *reinterpret_cast<const bf16x4*>(A + (mt * 16 + r) * K + kt * 16 + kq);
+#pragma unroll
+            for (int j = 0; j < 2; ++j) acc[mt][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b[j], acc[mt][j], 0, 0, 0);
+        }
+    }
+}
+
+// Forward over strings [0, n) of a (virtual) key array.  Writes y (the
+// network output, log10 of the predicted weight) and, for training, z1, z2
+// (pre-activations) and the bf16 features.
+__global__ __launch_bounds__(kThreads) void k_scorer_forward(ScorerFwdArgs A) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    FwdLds& L = *reinterpret_cast<FwdLds*>(smem);
+    const int tid = threadIdx.x;
+    const ScorerDev& S = A.net;
+    for (int i = tid; i < kScH * kScIn; i += kThreads) L.W1[i] = S.W1[i];
+    for (int i = tid; i < kScH * kScH; i += kThreads) L.W2[i] = S.W2[i];
+    for (int i = tid; i < kScH; i += kThreads) {
+        L.W3[i] = bf2f(S.W3[i]);
+        L.b1[i] = S.b1[i];
+        L.b2[i] = S.b2[i];
+    }
+    for (int i = tid; i < kScIn; i += kThreads) {
+        L.qmask[i] = S.qmask[i];
+        L.fscale[i] = S.fscale[i];
+        L.letter[i] = S.letter[i];
+    }
+    if (tid == 0) L.b3 = S.b3[0];
+    const uint64_t n = A.nf_ptr ? A.nf_ptr[0] + A.nb_ptr[0] : A.n;
+    const uint64_t nf = A.nf_ptr ? A.nf_ptr[0] : n;
+    const uint64_t ntiles = (n + kScTile - 1) / kScTile;
+    __syncthreads();
+    const int lane = tid & 63, wave = tid >> 6;
+
+    for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        // ---- features: 4 threads per string, 40 features each
+        {
+            const int s = tid >> 2, part = tid & 3;
+            const uint64_t i = tile * kScTile + s;
+            ulonglong2 x = make_ulonglong2(0, 0), z = make_ulonglong2(0, 0);
+            if (i < n) {
+                const uint64_t p = i < nf ? i : A.cap - 1 - (i - nf);
+                x = A.X[p];
+                z = A.Z[p];
+                if (A.xrot) x = rotl_n(x, A.xrot, A.nq);
+            }
+            const ulonglong2 mx = make_ulonglong2(x.x & ~z.x, x.y & ~z.y);
+            const ulonglong2 my = make_ulonglong2(x.x & z.x, x.y & z.y);
+            const ulonglong2 mz = make_ulonglong2(z.x & ~x.x, z.y & ~x.y);
+            const ulonglong2 ma = make_ulonglong2(x.x | z.x, x.y | z.y);
+            for (int f = part * (kScIn / 4); f < (part + 1) * (kScIn / 4); ++f) {
+                const uint16_t v = f2bf(feature(mx, my, mz, ma, L.qmask[f], L.letter[f], L.fscale[f]));
+                L.F[s * kScIn + f] = v;
+                if (A.f_out && i < n) A.f_out[i * kScIn + f] = v;
+            }
+        }
+        __syncthreads();
+
+        // ---- layer 1: z1 = F W1^T + b1, h1 = gelu(z1)
+        floatx4 acc[4][2];
+        layer64<kScIn>(L.F, L.W1, acc);
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                const int col = (2 * wave + j) * 16 + (lane & 15);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int row = mt * 16 + (lane >> 4) * 4 + q;
+                    const float zz = acc[mt][j][q] + L.b1[col];
+                    L.H[row * kScH + col] = f2bf(gelu(zz));
+                    const uint64_t i = tile * kScTile + row;
+                    if (A.z1_out && i < n) A.z1_out[i * kScH + col] = zz;
+                }
+            }
+        __syncthreads();
+
+        // ---- layer 2: z2 = h1 W2^T + b2, h2 = gelu(z2) (into the feature buffer)
+        layer64<kScH>(L.H, L.W2, acc);
+        __syncthreads();  // every wave is done reading F before h2 overwrites it
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                const int col = (2 * wave + j) * 16 + (lane & 15);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int row = mt * 16 + (lane >> 4) * 4 + q;
+                    const float zz = acc[mt][j][q] + L.b2[col];
+                    L.F[row * kScH + col] = f2bf(gelu(zz));
+                    const uint64_t i = tile * kScTile + row;
+                    if (A.z2_out && i < n) A.z2_out[i * kScH + col] = zz;
+                }
+            }
+        __syncthreads();
+
+        // ---- layer 3: y = h2 . W3 + b3 (4 threads per string, fp32)
+        {
+            const int s = tid >> 2, part = tid & 3;
+            float acc3 = 0.f;
+            for (int k = part * (kScH / 4); k < (part + 1) * (kScH / 4); ++k)
+                acc3 += bf2f(L.F[s * kScH + k]) * L.W3[k];
+            acc3 += __shfl_xor(acc3, 1, 64);
+            acc3 += __shfl_xor(acc3, 2, 64);
+            const uint64_t i = tile * kScTile + s;
+            if (part == 0 && i < n) A.y_out[i] = acc3 + L.b3;
+        }
+        __syncthreads();
+    }
+}
+
+// ---- backward, per sample: dy, dz2 = dy W3 * gelu'(z2), dz1 = (W2^T dz2) * gelu'(z1)
+__global__ __launch_bounds__(kThreads) void k_scorer_backward_rows(ScorerBwdArgs A) {
+    __shared__ float sW2[kScH * kScH];
+    __shared__ float sW3[kScH];
+    for (int i = threadIdx.x; i < kScH * kScH; i += kThreads) sW2[i] = bf2f(A.net.W2[i]);
+    for (int i = threadIdx.x; i < kScH; i += kThreads) sW3[i] = bf2f(A.net.W3[i]);
+    __syncthreads();
+    const float inv = 2.0f / static_cast<float>(A.n);
+    for (uint64_t s = blockIdx.x * uint64_t(kThreads) + threadIdx.x; s < A.n; s += uint64_t(gridDim.x) * kThreads) {
+        const float dy = inv * (A.y[s] - A.target[s]);
+        A.dy[s] = dy;
+        float dz2[kScH];
+#pragma unroll 8
+        for (int k = 0; k < kScH; ++k) {
+            dz2[k] = dy * sW3[k] * gelu_grad(A.z2[s * kScH + k]);
+            A.dz2[s * kScH + k] = dz2[k];
+        }
+        for (int j = 0; j < kScH; ++j) {
+            float h = 0.f;
+#pragma unroll 8
+            for (int k = 0; k < kScH; ++k) h += sW2[k * kScH + j] * dz2[k];
+            A.dz1[s * kScH + j] = h * gelu_grad(A.z1[s * kScH + j]);
+        }
+    }
+}
+
+// ---- weight gradients: out[i][j] = sum_s D[s][i] * B(s, j), j == J gives the
+// bias column (B = 1).  B is gelu(z) (mode 0, fp32 [N][J]) or bf16 features
+// (mode 1).  One workgroup per 16x16 output tile, samples in a fixed order.
+__global__ __launch_bounds__(kThreads) void k_scorer_atb(const float* __restrict__ D, int I, const void* __restrict__ B,
+                                                        int J, int mode, uint64_t N, float* __restrict__ outW,
+                                                        float* __restrict__ outB) {
+    __shared__ float sD[64][16];
+    __shared__ float sB[64][17];
+    const int ti = blockIdx.y * 16, tj = blockIdx.x * 16;
+    const int li = threadIdx.x >> 4, lj = threadIdx.x & 15;
+    float acc = 0.f;
+    for (uint64_t s0 = 0; s0 < N; s0 += 64) {
+        for (int t = threadIdx.x; t < 64 * 16; t += kThreads) {
+            const int ss = t >> 4, c = t & 15;
+            const uint64_t s = s0 + ss;
+            const int i = ti + c, j = tj + c;
+            sD[ss][c] = (s < N && i < I) ? D[s * I + i] : 0.f;
+            float bv = 0.f;
+            if (s < N) {
+                if (j == J) bv = 1.f;
+                else if (j < J) bv = mode == 0 ? gelu(static_cast<const float*>(B)[s * J + j])
+                                               : bf2f(static_cast<const uint16_t*>(B)[s * J + j]);
+            }
+            sB[ss][c] = bv;
+        }
+        __syncthreads();
+#pragma unroll 8
+        for (int ss = 0; ss < 64; ++ss) acc += sD[ss][li] * sB[ss][lj];
+        __syncthreads();
+    }
+    const int i = ti + li, j = tj + lj;
+    if (i < I && j < J) outW[i * J + j] = acc;
+    if (i < I && j == J) outB[i] = acc;
+}
+
+// ---- mean squared error (deterministic: fixed blocks, fixed tree)
+__global__ void k_scorer_loss(const float* __restrict__ y, const float* __restrict__ t, uint64_t n,
+                              double* __restrict__ out) {
+    __shared__ double s[kThreads];
+    double acc = 0.0;
+    for (uint64_t i = threadIdx.x; i < n; i += kThreads) {
+        const double r = double(y[i]) - double(t[i]);
+        acc += r * r;
+    }
+    s[threadIdx.x] = acc;
+    __syncthreads();
+    for (int o = kThreads / 2; o > 0; o >>= 1) {
+        if (threadIdx.x < o) s[threadIdx.x] += s[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = s[0] / double(n);
+}
+
+// ---- Adam on the fp32 master parameters; refreshes the bf16 weights.
+__global__ void k_scorer_adam(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,
+                              float* __restrict__ v, int n, float lr, float b1, float b2, float eps, float c1,
+                              float c2, ScorerDev net) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const float gi = g[i];
+        const float mi = b1 * m[i] + (1.f - b1) * gi;
+        const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+        m[i] = mi;
+        v[i] = vi;
+        const float pi = p[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+        p[i] = pi;
+        scorer_store_param(net, i, pi);
+    }
+}
+
+__global__ void k_scorer_set(const float* __restrict__ p, int n, ScorerDev net) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+        scorer_store_param(net, i, p[i]);
+}
+
+hipError_t launch_scorer_forward(const ScorerFwdArgs& a, hipStream_t s, int grid) {
+    static bool attr = false;
+    if (!attr) {
+        const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_scorer_forward),
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize, int(sizeof(FwdLds)));
+        if (e != hipSuccess) return e;
+        attr = true;
+    }
+    k_scorer_forward<<<dim3(grid), dim3(kThreads), sizeof(FwdLds), s>>>(a);
+    return hipGetLastError();
+}
+
+hipError_t launch_scorer_backward(const ScorerBwdArgs& a, const uint16_t* f, float* grad, hipStream_t s) {
+    const int nb = int(std::min<uint64_t>((a.n + kThreads - 1) / kThreads, 1024));
+    k_scorer_backward_rows<<<dim3(nb), dim3(kThreads), 0, s>>>(a);
+    // gradients straight into the flat parameter layout
+    k_scorer_atb<<<dim3((kScIn + 1 + 15) / 16, kScH / 16), dim3(kThreads), 0, s>>>(
+        a.dz1, kScH, f, kScIn, 1, a.n, grad + kScOffW1, grad + kScOffB1);
+    k_scorer_atb<<<dim3((kScH + 1 + 15) / 16, kScH / 16), dim3(kThreads), 0, s>>>(
+        a.dz2, kScH, a.z1, kScH, 0, a.n, grad + kScOffW2, grad + kScOffB2);
+    k_scorer_atb<<<dim3((kScH + 1 + 15) / 16, 1), dim3(kThreads), 0, s>>>(
+        a.dy, 1, a.z2, kScH, 0, a.n, grad + kScOffW3, grad + kScOffB3);
+    return hipGetLastError();
+}
+
+hipError_t launch_scorer_loss(const float* y, const float* t, uint64_t n, double* out, hipStream_t s) {
+    k_scorer_loss<<<1, kThreads, 0, s>>>(y, t, n, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_scorer_adam(float* p, const float* g, float* m, float* v, int n, float lr, int step,
+                              const ScorerDev& net, hipStream_t s) {
+    const float b1 = 0.9f, b2 = 0.999f;
+    const float c1 = 1.f - powf(b1, float(step)), c2 = 1.f - powf(b2, float(step));
+    k_scorer_adam<<<dim3((n + 255) / 256), dim3(256), 0, s>>>(p, g, m, v, n, lr, b1, b2, 1e-8f, c1, c2, net);
+    return hipGetLastError();
+}
+
+hipError_t launch_scorer_set(const float* p, int n, const ScorerDev& net, hipStream_t s) {
+    k_scorer_set<<<dim3((n + 255) / 256), dim3(256), 0, s>>>(p, n, net);
+    return hipGetLastError();
+}
+
+}  // namespace orqa
