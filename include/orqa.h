@@ -172,6 +172,18 @@ int pauli_sum_export(ps_handle* h, ps_pauli* keys, void* coeffs, size_t cap, siz
  * pauli_sum_load_scorer copy the scorer's network into the handle (the scorer
  *                       may be destroyed afterwards).
  */
+/*
+ * pauli_sum_set_graphs -- with enable != 0, every run of consecutive RX gates
+ * in a layer (e.g. the RX half of a Trotter step) is captured once into a HIP
+ * graph and replayed when the same gates meet the same buffers again, so a
+ * layer of 127 rotations costs one graph launch instead of 254 kernel
+ * launches.  Results are identical to the eager path.  Graphs are not used
+ * while timing is on, and are dropped when the capacity grows (the buffers
+ * move).  Capture uses a stream of the handle's own; replays go to the
+ * handle's stream.  enable == 0 drops the cached graphs.
+ */
+int pauli_sum_set_graphs(ps_handle* h, int enable);
+
 typedef struct ps_scorer ps_scorer;
 int ps_scorer_create(int n_qubits, const uint64_t* qmask, const uint8_t* letters, const float* scales,
                      void* hip_stream, ps_scorer** out);
@@ -197,6 +209,8 @@ int pauli_sum_load_scorer(ps_handle* h, const ps_scorer* s);
  *   cliff_launches fused Clifford / compaction launches, cliff_ms their time
  *   sort_passes    radix-sort passes, sort_ms their time
  *   bytes_per_string  key + coefficient bytes of one stored string
+ *   graph_replays, graph_captures  runs of RX gates replayed from / captured
+ *                  into HIP graphs (pauli_sum_set_graphs)
  */
 typedef struct {
     double updates, gates;
@@ -204,6 +218,7 @@ typedef struct {
     double cliff_launches, cliff_in, cliff_ms;
     double sort_passes, sort_elems, sort_ms;
     double bytes_per_string;
+    double graph_replays, graph_captures;
 } ps_stats;
 
 int pauli_sum_set_timing(ps_handle* h, int enable);

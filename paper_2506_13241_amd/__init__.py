@@ -26,7 +26,7 @@ EXPORTED_SYMBOLS = (
     "pauli_sum_truncate", "expectation_z", "pauli_sum_size", "pauli_sum_norm2", "pauli_sum_export",
     "pauli_sum_load_scorer", "pauli_sum_set_timing", "pauli_sum_stats", "ps_last_error",
     "ps_scorer_create", "ps_scorer_destroy", "ps_scorer_set_params", "ps_scorer_get_params", "ps_scorer_set_data",
-    "ps_scorer_forward", "ps_scorer_loss_grad", "ps_scorer_adam_step",
+    "ps_scorer_forward", "ps_scorer_loss_grad", "ps_scorer_adam_step", "pauli_sum_set_graphs",
 )
 N_SCORER_PARAMS = 37249
 
@@ -44,7 +44,7 @@ class ps_pauli(ctypes.Structure):
 class ps_stats(ctypes.Structure):
     _fields_ = [(name, ctypes.c_double) for name in (
         "updates", "gates", "rx_launches", "rx_in", "rx_out", "rx_ms", "cliff_launches", "cliff_in", "cliff_ms",
-        "sort_passes", "sort_elems", "sort_ms", "bytes_per_string")]
+        "sort_passes", "sort_elems", "sort_ms", "bytes_per_string", "graph_replays", "graph_captures")]
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -80,6 +80,7 @@ def load_library(path: str = LIB_PATH):
         "pauli_sum_set_timing": (I, [P, I]),
         "pauli_sum_stats": (I, [P, ctypes.POINTER(ps_stats), I]),
         "ps_last_error": (ctypes.c_char_p, []),
+        "pauli_sum_set_graphs": (I, [P, I]),
         "ps_scorer_create": (I, [I, P, P, P, P, ctypes.POINTER(P)]),
         "ps_scorer_destroy": (I, [P]),
         "ps_scorer_set_params": (I, [P, P, S]),
@@ -197,6 +198,11 @@ class PauliSum:
 
     def set_timing(self, enable: bool = True):
         _check(_lib.pauli_sum_set_timing(self._h, int(enable)))
+        return self
+
+    def set_graphs(self, enable: bool = True):
+        _check(_lib.pauli_sum_set_graphs(self._h, int(enable)))
+        return self
 
     def stats(self, reset: bool = False) -> dict:
         st = ps_stats()

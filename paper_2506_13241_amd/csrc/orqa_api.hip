@@ -148,6 +148,17 @@ struct ps_handle {
     size_t ev_used = 0;
     double ms[3] = {0, 0, 0};
     double sort_passes = 0, sort_elems = 0, gates = 0;
+    // captured runs of RX stages (see run_rx_graph)
+    bool graphs = false;
+    hipStream_t cap_stream = nullptr;
+    uint64_t alloc_gen = 0;  // bumped whenever device buffers move
+    struct GraphEntry {
+        uint64_t key;
+        size_t n_stages;
+        hipGraphExec_t exec;
+    };
+    std::vector<GraphEntry> graph_cache;
+    double graph_replays = 0, graph_captures = 0;
 };
 
 namespace {
@@ -316,6 +327,8 @@ int ev_collect(ps_handle* h) {
     return PS_OK;
 }
 
+void drop_graphs(ps_handle* h);
+
 // Grow capacity to at least `need`, keeping state buffer `keep` (front and back
 // runs) and its sizes; the other buffer's contents are discarded.  Everything
 // but the kept buffer is released first, so the peak is the kept buffer plus
@@ -325,6 +338,8 @@ int grow(ps_handle* h, int keep, uint64_t need) {
     Ctrl c;
     int rc = read_ctrl(h, &c);
     if (rc) return rc;
+    drop_graphs(h);  // captured launches point at the buffers about to move
+    h->alloc_gen += 1;
     free_state(&h->buf[1 - keep]);
     {
         Aux old = take_aux(h);
@@ -462,7 +477,9 @@ int enqueue_compact(ps_handle* h, int in, int out, int mx_in, int mx_out, double
     return ev_end(h, slot);
 }
 
-int enqueue_rx(ps_handle* h, int in, int out, int mx_in, int mx_out, double eps_in, const GateTrig& g) {
+int enqueue_rx(ps_handle* h, int in, int out, int mx_in, int mx_out, double eps_in, const GateTrig& g,
+               hipStream_t stream = nullptr, bool timed = true) {
+    if (!stream) stream = h->stream;
     RxArgs a{};
     a.ctrl = h->ctrl;
     a.in_buf = in;
@@ -481,12 +498,76 @@ int enqueue_rx(ps_handle* h, int in, int out, int mx_in, int mx_out, double eps_
     a.max_tiles = h->max_tiles;
     a.eps_in = eps_in;
     a.nq = h->nq;
-    HIP_TRY(launch_rx_partition(a, h->stream));
-    size_t slot;
-    int rc = ev_begin(h, 0, &slot);
-    if (rc) return rc;
-    HIP_TRY(launch_rx(a, g, h->dtype, h->LP, h->stream, h->grid));
+    HIP_TRY(launch_rx_partition(a, stream));
+    size_t slot = SIZE_MAX;
+    if (timed) {
+        int rc = ev_begin(h, 0, &slot);
+        if (rc) return rc;
+    }
+    HIP_TRY(launch_rx(a, g, h->dtype, h->LP, stream, h->grid));
     return ev_end(h, slot);
+}
+
+void drop_graphs(ps_handle* h) {
+    for (auto& e : h->graph_cache) (void)hipGraphExecDestroy(e.exec);
+    h->graph_cache.clear();
+}
+
+uint64_t fnv1a(uint64_t hsh, const void* p, size_t n) {
+    const unsigned char* b = static_cast<const unsigned char*>(p);
+    for (size_t i = 0; i < n; ++i) hsh = (hsh ^ b[i]) * 1099511628211ull;
+    return hsh;
+}
+
+constexpr size_t kGraphCacheMax = 8;
+
+// Enqueue the RX stages trigs[0..n) as one HIP graph: captured on the
+// handle's capture stream on first use, replayed on the handle's stream when
+// the same run of gates meets the same buffers, parity, pending threshold and
+// capacity again.  The launches read sizes and maxima from the control block
+// on the device, so a replay needs no host input.  Stage k reads buffer
+// (cur + k) % 2 and uses pend0 as its pending threshold for k = 0, eps after.
+int run_rx_graph(ps_handle* h, const std::vector<GateTrig>& trigs, double pend0, double eps) {
+    const size_t n = trigs.size();
+    uint64_t key = 1469598103934665603ull;
+    const uint64_t hdr[4] = {h->alloc_gen, uint64_t(h->cap), uint64_t(h->cur | (h->mx << 1)), uint64_t(n)};
+    key = fnv1a(key, hdr, sizeof hdr);
+    key = fnv1a(key, &pend0, sizeof pend0);
+    key = fnv1a(key, &eps, sizeof eps);
+    for (const GateTrig& t : trigs) key = fnv1a(key, &t, sizeof t);
+    for (const auto& e : h->graph_cache)
+        if (e.key == key && e.n_stages == n) {
+            HIP_TRY(hipGraphLaunch(e.exec, h->stream));
+            h->graph_replays += 1;
+            return PS_OK;
+        }
+    if (!h->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
+    HIP_TRY(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
+    int cur = h->cur, mx = h->mx, rc = PS_OK;
+    for (size_t k = 0; k < n && rc == PS_OK; ++k) {
+        rc = enqueue_rx(h, cur, 1 - cur, mx, 1 - mx, k == 0 ? pend0 : eps, trigs[k], h->cap_stream, false);
+        cur = 1 - cur;
+        mx = 1 - mx;
+    }
+    hipGraph_t graph = nullptr;
+    const hipError_t ec = hipStreamEndCapture(h->cap_stream, &graph);
+    if (rc != PS_OK || ec != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        (void)hipGetLastError();
+        return rc != PS_OK ? rc : fail(PS_ERR_HIP, "hipStreamEndCapture: %s", hipGetErrorString(ec));
+    }
+    hipGraphExec_t exec = nullptr;
+    const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ei != hipSuccess) return fail(PS_ERR_HIP, "hipGraphInstantiate: %s", hipGetErrorString(ei));
+    if (h->graph_cache.size() >= kGraphCacheMax) {
+        (void)hipGraphExecDestroy(h->graph_cache.front().exec);
+        h->graph_cache.erase(h->graph_cache.begin());
+    }
+    h->graph_cache.push_back({key, n, exec});
+    h->graph_captures += 1;
+    HIP_TRY(hipGraphLaunch(exec, h->stream));
+    return PS_OK;
 }
 
 // Re-sort buffer `b` (front only, with group ranks) by (rank, z).  Returns the
@@ -729,6 +810,8 @@ int pauli_sum_destroy(ps_handle* h) {
     if (h->cgens) (void)hipFree(h->cgens);
     for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
     if (h->has_scorer) scorer_free(&h->scorer);
+    drop_graphs(h);
+    if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
     delete h;
     return PS_OK;
 }
@@ -883,6 +966,22 @@ int apply_rotation_layer(ps_handle* h, const ps_pauli* gens, const double* theta
                 // the gates leave every magnitude (and the max) unchanged:
                 // only the pending threshold of this layer is recorded
                 if (eps > 0.0) h->pend = std::max(h->pend, eps);
+                continue;
+            }
+            if (s.kind == ST_RX && h->graphs && !h->timing) {
+                size_t j = si;
+                std::vector<GateTrig> trigs;
+                while (j < stages.size() && stages[j].kind == ST_RX) trigs.push_back(stages[j++].trig);
+                rc = run_rx_graph(h, trigs, h->pend, eps);
+                if (rc) return rc;
+                for (size_t k = si; k < j; ++k) {
+                    launched.push_back({k, h->cur, h->mx, h->xrot, h->pend});
+                    h->xrot = (h->xrot + 1) % h->nq;
+                    h->cur = 1 - h->cur;
+                    h->mx = 1 - h->mx;
+                    h->pend = eps;
+                }
+                si = j - 1;  // the loop increment moves past the run
                 continue;
             }
             launched.push_back({si, h->cur, h->mx, h->xrot, h->pend});
@@ -1113,7 +1212,10 @@ int pauli_sum_stats(ps_handle* h, ps_stats* out, int reset) {
     out->sort_elems = h->sort_elems;
     out->sort_ms = h->ms[2];
     out->bytes_per_string = double(2 * sizeof(ulonglong2) + h->csize);
+    out->graph_replays = h->graph_replays;
+    out->graph_captures = h->graph_captures;
     if (reset) {
+        h->graph_replays = h->graph_captures = 0;
         c.cnt_updates = c.cnt_rx_in = c.cnt_rx_out = c.cnt_rx_launches = 0;
         c.cnt_cliff_in = c.cnt_cliff_launches = 0;
         HIP_TRY(hipMemcpyAsync(&h->ctrl->cnt_updates, &c.cnt_updates, 6 * sizeof(uint64_t), hipMemcpyHostToDevice,
@@ -1122,6 +1224,17 @@ int pauli_sum_stats(ps_handle* h, ps_stats* out, int reset) {
         h->ms[0] = h->ms[1] = h->ms[2] = 0;
         h->sort_passes = h->sort_elems = h->gates = 0;
     }
+    return PS_OK;
+}
+
+int pauli_sum_set_graphs(ps_handle* h, int enable) {
+    if (!h) return fail(PS_ERR_INVALID, "NULL argument");
+    if (h->broken) return fail(PS_ERR_DEVICE, "handle is no longer usable");
+    if (!enable) {
+        HIP_TRY(hipStreamSynchronize(h->stream));
+        drop_graphs(h);
+    }
+    h->graphs = enable != 0;
     return PS_OK;
 }
 

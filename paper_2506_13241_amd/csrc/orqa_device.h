@@ -110,6 +110,8 @@ __device__ __forceinline__ uint32_t ld32(const uint32_t* p) {
 // "not ready", so status arrays never need clearing between launches.
 constexpr uint64_t kValMask = (1ull << 38) - 1;
 constexpr uint64_t kLookbackTicks = 200000000ull;  // ~2 s of the 100 MHz wall clock
+constexpr int kLbPer = 1;                          // status words per lane per look-back round trip (wider windows measured slower)
+constexpr int kLbWin = 64 * kLbPer;
 
 __device__ __forceinline__ uint64_t st_pack(uint32_t ep, uint32_t fl, uint64_t v) {
     return (static_cast<uint64_t>(ep & 0xFFFFFFu) << 40) | (static_cast<uint64_t>(fl) << 38) | (v & kValMask);
@@ -135,36 +137,57 @@ __device__ __forceinline__ uint64_t lookback_wave(uint64_t* st, uint64_t stride,
     int64_t base = static_cast<int64_t>(tile) - 1;
     const uint64_t t0 = wall_clock64();
     bool timed_out = false;
+    // Window of 64 * kLbPer predecessors per round trip: lane l holds distances
+    // l*kLbPer .. l*kLbPer + kLbPer-1 (distance 0 is the nearest predecessor).
     while (true) {
-        const int64_t j = base - lane;
-        uint64_t v = 0;
-        uint32_t fl = 2;
+        uint64_t v[kLbPer];
+        int di = kLbWin, dr = kLbWin;
         while (true) {
-            if (j >= 0) {
-                v = ld_acq(st + j * stride);
-                fl = st_flag(v, ep);
-            } else {
-                v = 0;
-                fl = 2;
+            int fi_l = kLbPer, fr_l = kLbPer;
+#pragma unroll
+            for (int k = 0; k < kLbPer; ++k) {
+                const int64_t j = base - (lane * kLbPer + k);
+                v[k] = j >= 0 ? ld_acq(st + j * stride) : 0ull;
             }
-            if (__all(fl != 0u)) break;
+#pragma unroll
+            for (int k = kLbPer - 1; k >= 0; --k) {
+                const int64_t j = base - (lane * kLbPer + k);
+                const uint32_t fl = j >= 0 ? st_flag(v[k], ep) : 2u;  // before tile 0: inclusive 0
+                if (fl == 2u) fi_l = k;
+                if (fl == 0u) fr_l = k;
+            }
+            // Only the run from the nearest predecessor up to the first
+            // inclusive prefix matters; tiles beyond it may still be loading.
+            const uint64_t il = __ballot(fi_l < kLbPer);
+            const uint64_t pl = __ballot(fr_l < kLbPer);
+            if (il) {
+                const int L = __ffsll(static_cast<unsigned long long>(il)) - 1;
+                di = L * kLbPer + __shfl(fi_l, L, 64);
+            }
+            if (pl) {
+                const int L = __ffsll(static_cast<unsigned long long>(pl)) - 1;
+                dr = L * kLbPer + __shfl(fr_l, L, 64);
+            }
+            if (dr > di || dr == kLbWin) break;
+            di = dr = kLbWin;
             if (__any(wall_clock64() - t0 > kLookbackTicks)) {
                 timed_out = true;
                 break;
             }
-            __builtin_amdgcn_s_sleep(2);
+            __builtin_amdgcn_s_sleep(1);
         }
         if (timed_out) {
             if (lane == 0) atomicOr(err, kErrLookback);
             excl = 0;
             break;
         }
-        const uint64_t incl = __ballot(fl == 2u);
-        const int stop = incl ? (__ffsll(static_cast<unsigned long long>(incl)) - 1) : 63;
-        const uint64_t c = (lane <= stop) ? (v & kValMask) : 0ull;
+        uint64_t c = 0;
+#pragma unroll
+        for (int k = 0; k < kLbPer; ++k)
+            if (lane * kLbPer + k <= di) c += v[k] & kValMask;
         excl += wave_sum_u64(c);
-        if (incl) break;
-        base -= 64;
+        if (di < kLbWin) break;
+        base -= kLbWin;
     }
     if (lane == 0) st_rel(st + tile * stride, st_pack(ep, 2, excl + agg));
     return excl;

@@ -6,13 +6,14 @@
    Ising steps with magnitude truncation at `sample_eps`; after step k keep a
    sample of the live strings, stratified by log10(|c| / max|c|) so that the
    band where truncation decisions are taken is well covered.
-2. Labels: the weight of string I sampled after k steps is
-   g_I = <0| (remaining steps applied to sigma_I) |0>, the factor with which
-   its coefficient reaches <Z> (Heisenberg picture, Eq. expectation; the sum
-   is linear in the strings).  The remaining steps are capped at
-   `horizon`; 32 sampled strings are propagated at once as 32 coefficient
-   lanes (lane a starts as the a-th string with coefficient 1), with lane-wise
-   magnitude truncation at `label_eps`.  Target: log10(|g_I| + floor).
+2. Labels: the weight of a sampled string I is max over h = 1..horizon of
+   |g_I,h|, g_I,h = <0| (h further steps applied to sigma_I) |0> being the
+   factor with which its coefficient reaches <Z> h steps later (Heisenberg
+   picture, Eq. expectation; <Z> is linear in the strings), so a string that
+   matters to any of the next `horizon` readouts scores high.  32 sampled
+   strings are propagated at once as 32 binary32 coefficient lanes (lane a
+   starts as the a-th string with coefficient 1), dropping paths whose weight
+   falls below `label_eps` (absolute).  Target: log10(|g_I| + floor).
 3. Fit: full-batch Adam on the mean squared error, with the library's own
    forward, backward and Adam kernels.
 
@@ -79,35 +80,58 @@ def sample_strings(n_qubits, edges, obs_qubit, theta, sample_steps, sample_eps, 
     return np.concatenate(keys), np.concatenate(step)
 
 
-def label_strings(n_qubits, edges, theta, keys, remaining, label_eps, lanes=32, log=None):
-    """g_I for each key: <Z> after `remaining[i]` further steps from sigma_I."""
+def _label_batch(n_qubits, zz, rx, keys, horizon, label_eps, lanes, reduce="max"):
+    """max over h = 1..horizon of |g_h| for up to `lanes` keys, one lane each.
+    An identity string with coefficient 1 in every lane anchors the lane
+    maximum at 1, so the lane-wise relative threshold acts as an absolute one:
+    paths whose weight falls below label_eps are dropped (without the anchor, a
+    string with many Y/Z letters spawns ~2^w children of nearly equal size that
+    a relative threshold never removes).  The anchor commutes with every gate
+    and adds exactly 1 to <Z>."""
+    m = len(keys)
+    words = np.concatenate([np.zeros((1, 4), dtype=np.uint64), keys])
+    coeffs = np.zeros((m + 1, lanes))
+    coeffs[0, :] = 1.0
+    coeffs[1 + np.arange(m), np.arange(m)] = 1.0
+    op = PauliSum(n_qubits, words, coeffs, dtype=1)
+    best = np.zeros(m)
+    try:
+        for h in range(horizon):
+            op.apply_rotation_layer(zz, label_eps).apply_rotation_layer(rx, label_eps)
+            if reduce == "max" or h == horizon - 1:
+                best = np.maximum(best, np.abs(op.expectation_z()[:m] - 1.0))
+        return best
+    finally:
+        op.close()
+
+
+def label_strings(n_qubits, edges, theta, keys, horizon, label_eps, lanes=32, log=None, reduce="max"):
+    """max over h = 1..horizon of |g_I,h| (reduce="max") or |g_I,horizon|
+    (reduce="last"), g_I,h being <Z> after h further steps from sigma_I, with
+    paths below label_eps dropped.  Returns (g, ok);
+    ok is False for keys whose batch exceeded device memory even alone (their g
+    is 0)."""
+    from . import PsError
     zz, rx = w.kicked_ising_step(w.Lattice(n_qubits, [tuple(e) for e in edges]), theta, lanes=lanes)
     g = np.zeros(len(keys))
-    order = np.argsort(remaining, kind="stable")
+    ok = np.ones(len(keys), dtype=bool)
     t0 = time.time()
-    for b in range(0, len(keys), lanes):
-        sel = order[b:b + lanes]
-        r = int(remaining[sel[0]])
-        sel = sel[remaining[sel] == r]  # one horizon per batch
-        coeffs = np.zeros((len(sel), lanes))
-        coeffs[np.arange(len(sel)), np.arange(len(sel))] = 1.0
-        op = PauliSum(n_qubits, keys[sel], coeffs)
-        for _ in range(r):
-            op.apply_rotation_layer(zz, label_eps).apply_rotation_layer(rx, label_eps)
-        g[sel] = op.expectation_z()[: len(sel)]
-        op.close()
-        if log and (b // lanes) % log == 0:
-            _say(f"  labels {b + len(sel)}/{len(keys)} (horizon {r}, {time.time() - t0:.1f} s)")
-    return g
-
-
-def label_strings_all(n_qubits, edges, theta, keys, remaining, label_eps, lanes=32, log=20):
-    """Batches never mix horizons: keys are grouped by horizon first."""
-    g = np.zeros(len(keys))
-    for r in np.unique(remaining):
-        idx = np.flatnonzero(remaining == r)
-        g[idx] = label_strings(n_qubits, edges, theta, keys[idx], remaining[idx], label_eps, lanes, log)
-    return g
+    todo = [np.arange(b, min(b + lanes, len(keys))) for b in range(0, len(keys), lanes)]
+    done = 0
+    while todo:
+        sel = todo.pop(0)
+        try:
+            g[sel] = _label_batch(n_qubits, zz, rx, keys[sel], horizon, label_eps, lanes, reduce)
+            done += len(sel)
+        except PsError:
+            if len(sel) == 1:
+                ok[sel] = False
+                done += 1
+            else:  # split the batch and retry the halves
+                todo[:0] = [sel[: len(sel) // 2], sel[len(sel) // 2:]]
+        if log and done and (done // lanes) % log == 0 and len(sel):
+            _say(f"  labels {done}/{len(keys)} ({time.time() - t0:.1f} s)")
+    return g, ok
 
 
 def fit(n_qubits, table, keys, targets, iters, lr, seed, log=100):
@@ -130,13 +154,14 @@ def main(argv=None):
     ap.add_argument("--obs", type=int, default=None)
     ap.add_argument("--theta", type=float, default=0.8)
     ap.add_argument("--sample-steps", type=int, default=8)
-    ap.add_argument("--sample-eps", type=float, default=1e-6)
-    ap.add_argument("--per-step", type=int, default=4096)
+    ap.add_argument("--sample-eps", type=float, default=1e-4)
+    ap.add_argument("--per-step", type=int, default=8192)
     ap.add_argument("--horizon", type=int, default=3)
-    ap.add_argument("--label-eps", type=float, default=1e-4)
-    ap.add_argument("--floor", type=float, default=1e-5)
-    ap.add_argument("--iters", type=int, default=2000)
-    ap.add_argument("--lr", type=float, default=2e-3)
+    ap.add_argument("--label-eps", type=float, default=1e-3)
+    ap.add_argument("--label", default="max", choices=["max", "last"])
+    ap.add_argument("--floor", type=float, default=1e-3)
+    ap.add_argument("--iters", type=int, default=3000)
+    ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--seed", type=int, default=20250616)
     ap.add_argument("--out", required=True)
     a = ap.parse_args(argv)
@@ -147,15 +172,16 @@ def main(argv=None):
     table = S.feature_table(n, edges, obs)
     t0 = time.time()
     keys, step = sample_strings(n, edges, obs, a.theta, a.sample_steps, a.sample_eps, a.per_step, a.seed)
-    remaining = np.minimum(a.sample_steps - step, a.horizon)
     _say(f"sampled {len(keys)} strings in {time.time() - t0:.1f} s")
     t1 = time.time()
-    g = label_strings_all(n, edges, a.theta, keys, remaining, a.label_eps)
+    g, ok = label_strings(n, edges, a.theta, keys, a.horizon, a.label_eps, log=20, reduce=a.label)
+    keys, g = keys[ok], g[ok]
     targets = np.log10(np.abs(g) + a.floor).astype(np.float32)
     _say(f"labelled in {time.time() - t1:.1f} s; target mean {targets.mean():.3f} sd {targets.std():.3f}")
     sc, first, last = fit(n, table, keys, targets, a.iters, a.lr, a.seed)
     meta = dict(lattice=a.lattice, obs=obs, theta=a.theta, sample_steps=a.sample_steps, sample_eps=a.sample_eps,
-                per_step=a.per_step, horizon=a.horizon, label_eps=a.label_eps, floor=a.floor, iters=a.iters,
+                per_step=a.per_step, horizon=a.horizon, label=a.label, label_eps=a.label_eps, floor=a.floor,
+                iters=a.iters,
                 lr=a.lr, seed=a.seed, n_samples=len(keys), loss_first=first, loss_last=last,
                 target_sd=float(targets.std()))
     S.save_params(a.out, sc.get_params(), meta)
