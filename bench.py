@@ -36,13 +36,24 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+KERNEL_SOURCES = ("orqa_kernels.hip", "orqa_device.h", "orqa_internal.h")
+
+
+def kernel_source_sha():
+    """sha256 (16 hex digits) over the sources the RX merge kernel is built from."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, "paper_2506_13241_amd", "csrc", name), "rb").read())
+    return h.hexdigest()[:16]
+
+
 def measured_traffic():
     """HBM bytes per RX merge launch from the committed rocprofv3 summary, or
     None when the kernel source changed since those counters were taken."""
     import glob
     import hashlib
-    src = os.path.join(ROOT, "paper_2506_13241_amd", "csrc", "orqa_kernels.hip")
-    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    sha = kernel_source_sha()
     for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "k_rx_merge__*fp64.md"))):
         fields = {}
         for line in open(path):
@@ -101,6 +112,10 @@ def main():
     ap.add_argument("--theta", type=float, default=0.8)
     ap.add_argument("--eps", type=float, default=1e-4)
     ap.add_argument("--dtype", choices=["f64", "f32"], default="f64")
+    ap.add_argument("--reference-f64", action="store_true",
+                    help="after the run, repeat it untimed in binary64 (magnitude rule) and report |delta <Z62>| per step")
+    ap.add_argument("--trunc", choices=["magnitude", "learned"], default="magnitude",
+                    help="learned: the committed trained scorer (127q, Z62, theta 0.8) on top of the magnitude rule")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--verbose", action="store_true")
@@ -112,10 +127,16 @@ def main():
         x = torch.empty(args.copy_probe // 4, dtype=torch.float32, device="cuda").fill_(1.0)
         y = torch.empty_like(x)
         torch.cuda.synchronize()
-        for _ in range(5):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
+        for i in range(5):
+            ev[i].record()
             y.copy_(x)
+        ev[5].record()
         torch.cuda.synchronize()
-        print(json.dumps({"copy_probe_bytes": x.numel() * 4, "launches": 5}))
+        ms = [ev[i].elapsed_time(ev[i + 1]) for i in range(1, 5)]  # first copy is a warm-up
+        gbs = 2 * x.numel() * 4 / (sum(ms) / len(ms) * 1e-3) / 1e9
+        print(json.dumps({"copy_probe_bytes": x.numel() * 4, "launches": 5, "mean_ms": sum(ms) / len(ms),
+                          "read_plus_write_GBps": round(gbs, 1)}))
         return
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -135,11 +156,19 @@ def main():
     terms, coef = w.single_pauli_term(lat.n, {62: "Z"})
     dtype = P.PS_F64 if args.dtype == "f64" else P.PS_F32
     ps = P.PauliSum(lat.n, terms, coef, dtype=dtype, capacity=1 << 22)
+    mode = P.PS_TRUNC_MAGNITUDE
+    if args.trunc == "learned":
+        from paper_2506_13241_amd import scorer as S
+        params, _ = S.load_params(os.path.join(ROOT, "paper_2506_13241_amd", "data",
+                                               "scorer_eagle127_z62_theta0.8.npz"))
+        sc = P.PsScorer(lat.n, *S.feature_table(lat.n, lat.edges, 62)).set_params(params)
+        ps.load_scorer(sc)
+        mode = P.PS_TRUNC_LEARNED
 
     ez_all = []
     t_start = time.perf_counter()
     for s in range(args.warmup):
-        ps.apply_rotation_layer(zz, args.eps).apply_rotation_layer(rx, args.eps)
+        ps.apply_rotation_layer(zz, args.eps, mode).apply_rotation_layer(rx, args.eps, mode)
         ez_all.append(float(ps.expectation_z()[0]))
         if args.verbose:
             log(f"warmup step {s + 1}: |O|={ps.size()} <Z62>={ez_all[-1]:.12f} t={time.perf_counter() - t_start:.2f}s")
@@ -149,7 +178,7 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for s in range(args.steps):
-        ps.apply_rotation_layer(zz, args.eps).apply_rotation_layer(rx, args.eps)
+        ps.apply_rotation_layer(zz, args.eps, mode).apply_rotation_layer(rx, args.eps, mode)
         ez_all.append(float(ps.expectation_z()[0]))
         if args.verbose:
             log(f"timed step {args.warmup + s + 1}: <Z62>={ez_all[-1]:.12f} t={time.perf_counter() - t0:.2f}s")
@@ -191,8 +220,28 @@ def main():
         "sort_passes": int(st["sort_passes"]),
         "paper_time_per_gate_ms": round(dt / args.steps / 271 * 1e3, 4),
     }
+    if st["score_launches"] > 0:
+        flop = 2 * (160 * 128 + 128 * 128 + 128) * st["score_in"]
+        extra["scorer"] = {
+            "kernel": "k_scorer_forward", "launches": int(st["score_launches"]), "strings": int(st["score_in"]),
+            "ms_total": round(st["score_ms"], 3),
+            "tflops": round(flop / (st["score_ms"] * 1e-3) / 1e12, 2) if st["score_ms"] > 0 else None,
+            "frac_of_bf16_peak": round(flop / (st["score_ms"] * 1e-3) / 2.5e15, 4) if st["score_ms"] > 0 else None,
+        }
+    if args.reference_f64:
+        ps.close()
+        ref = P.PauliSum(lat.n, terms, coef, dtype=P.PS_F64)
+        ez_ref = []
+        for s in range(args.warmup + args.steps):
+            ref.apply_rotation_layer(zz, args.eps).apply_rotation_layer(rx, args.eps)
+            ez_ref.append(float(ref.expectation_z()[0]))
+        ref.close()
+        d = [abs(a - b) for a, b in zip(ez_all, ez_ref)]
+        extra["ez_z62_f64_magnitude"] = ez_ref
+        extra["dz_vs_f64_per_step"] = d
+        extra["dz_vs_f64_max"] = max(d)
     cpu = None
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and args.trunc == "magnitude":
         cpu, ez_cpu = cpu_baseline(args.theta, args.eps, args.cpu_budget)
         k = min(len(ez_cpu), len(ez_all))
         if k:
@@ -213,7 +262,9 @@ def main():
         "data": "synthetic: deterministic kicked-Ising circuit, no dataset",
         "config": {
             "workload": f"kicked Ising 127q heavy-hex, O0=Z62, theta_h={args.theta}, theta_zz=-pi/2, "
-                        f"eps0={args.eps} per gate, Trotter steps {args.warmup + 1}-{args.warmup + args.steps}",
+                        f"eps0={args.eps} per gate"
+                        + (" + learned truncation once per step" if args.trunc == "learned" else "")
+                        + f", Trotter steps {args.warmup + 1}-{args.warmup + args.steps}",
             "qubits": 127,
             "gates_per_step": 271,
         },

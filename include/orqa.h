@@ -211,6 +211,8 @@ int pauli_sum_load_scorer(ps_handle* h, const ps_scorer* s);
  *   bytes_per_string  key + coefficient bytes of one stored string
  *   graph_replays, graph_captures  runs of RX gates replayed from / captured
  *                  into HIP graphs (pauli_sum_set_graphs)
+ *   score_launches, score_in, score_ms  learned-scorer launches, strings
+ *                  scored and their kernel time (PS_TRUNC_LEARNED)
  */
 typedef struct {
     double updates, gates;
@@ -219,6 +221,7 @@ typedef struct {
     double sort_passes, sort_elems, sort_ms;
     double bytes_per_string;
     double graph_replays, graph_captures;
+    double score_launches, score_in, score_ms;
 } ps_stats;
 
 int pauli_sum_set_timing(ps_handle* h, int enable);

@@ -44,7 +44,8 @@ class ps_pauli(ctypes.Structure):
 class ps_stats(ctypes.Structure):
     _fields_ = [(name, ctypes.c_double) for name in (
         "updates", "gates", "rx_launches", "rx_in", "rx_out", "rx_ms", "cliff_launches", "cliff_in", "cliff_ms",
-        "sort_passes", "sort_elems", "sort_ms", "bytes_per_string", "graph_replays", "graph_captures")]
+        "sort_passes", "sort_elems", "sort_ms", "bytes_per_string", "graph_replays", "graph_captures",
+        "score_launches", "score_in", "score_ms")]
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_}

@@ -144,9 +144,9 @@ struct ps_handle {
     // measurement: event pairs around launches, folded into host totals at syncs
     bool timing = false;
     std::vector<hipEvent_t> ev_pool;
-    std::vector<int> ev_kind;  // 0 rx merge, 1 clifford/compaction, 2 sort pass
+    std::vector<int> ev_kind;  // 0 rx merge, 1 clifford/compaction, 2 sort pass, 3 learned scorer
     size_t ev_used = 0;
-    double ms[3] = {0, 0, 0};
+    double ms[4] = {0, 0, 0, 0};
     double sort_passes = 0, sort_elems = 0, gates = 0;
     // captured runs of RX stages (see run_rx_graph)
     bool graphs = false;
@@ -439,10 +439,11 @@ int enqueue_compact(ps_handle* h, int in, int out, int mx_in, int mx_out, double
         f.xrot = h->xrot;
         f.nq = h->nq;
         f.y_out = h->gscore;
+        f.counters = &h->ctrl->aux[0];
         size_t slot;
-        int rc = ev_begin(h, 1, &slot);
+        int rc = ev_begin(h, 3, &slot);
         if (rc) return rc;
-        HIP_TRY(launch_scorer_forward(f, h->stream, h->grid / 4));
+        HIP_TRY(launch_scorer_forward(f, h->stream, h->grid / 2));  // two 512-thread workgroups per CU
         rc = ev_end(h, slot);
         if (rc) return rc;
     }
@@ -1214,8 +1215,14 @@ int pauli_sum_stats(ps_handle* h, ps_stats* out, int reset) {
     out->bytes_per_string = double(2 * sizeof(ulonglong2) + h->csize);
     out->graph_replays = h->graph_replays;
     out->graph_captures = h->graph_captures;
+    out->score_in = double(c.aux[0]);
+    out->score_launches = double(c.aux[1]);
+    out->score_ms = h->ms[3];
     if (reset) {
         h->graph_replays = h->graph_captures = 0;
+        h->ms[3] = 0;
+        const uint64_t z2[2] = {0, 0};
+        HIP_TRY(hipMemcpyAsync(&h->ctrl->aux[0], z2, sizeof z2, hipMemcpyHostToDevice, h->stream));
         c.cnt_updates = c.cnt_rx_in = c.cnt_rx_out = c.cnt_rx_launches = 0;
         c.cnt_cliff_in = c.cnt_cliff_launches = 0;
         HIP_TRY(hipMemcpyAsync(&h->ctrl->cnt_updates, &c.cnt_updates, 6 * sizeof(uint64_t), hipMemcpyHostToDevice,

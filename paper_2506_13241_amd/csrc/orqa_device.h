@@ -174,7 +174,7 @@ __device__ __forceinline__ uint64_t lookback_wave(uint64_t* st, uint64_t stride,
                 timed_out = true;
                 break;
             }
-            __builtin_amdgcn_s_sleep(1);
+            __builtin_amdgcn_s_sleep(16);
         }
         if (timed_out) {
             if (lane == 0) atomicOr(err, kErrLookback);
@@ -226,7 +226,15 @@ __device__ __forceinline__ uint64_t lookback_thread(uint64_t* st, uint64_t strid
 
 // Dynamic tile acquisition for persistent look-back kernels.
 __device__ __forceinline__ uint32_t acquire_tile(Ctrl* ctrl, uint32_t* s_tile) {
-    if (threadIdx.x == 0) *s_tile = atomicAdd(&ctrl->tile_counter, 1u);
+    // Tiles are dealt round-robin to S = min(kTileStreams, gridDim.x) streams
+    // of workgroups (stream = blockIdx modulo S), each with a counter of its
+    // own, so no single address takes every acquisition.  Every stream has a
+    // workgroup, and a stream takes its tiles in increasing order.
+    if (threadIdx.x == 0) {
+        const uint32_t S = gridDim.x < kTileStreams ? gridDim.x : kTileStreams;
+        const uint32_t st = blockIdx.x % S;
+        *s_tile = atomicAdd(&ctrl->tile_ctr[st][0], 1u) * S + st;
+    }
     __syncthreads();
     const uint32_t t = *s_tile;
     __syncthreads();
@@ -244,6 +252,8 @@ __device__ __forceinline__ bool finish_launch(Ctrl* ctrl) {
         const uint32_t d = atomicAdd(&ctrl->done_counter, 1u);
         if (d == gridDim.x - 1) {
             __threadfence();
+            for (uint32_t i = 0; i < kTileStreams; ++i)
+                __hip_atomic_store(&ctrl->tile_ctr[i][0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             __hip_atomic_store(&ctrl->tile_counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             __hip_atomic_store(&ctrl->done_counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             __hip_atomic_store(&ctrl->epoch, ctrl->epoch + 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);

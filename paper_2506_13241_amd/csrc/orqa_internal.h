@@ -33,6 +33,8 @@ constexpr int kReduceBlocks = 512;
 // a "virtual array": a front run at [0, nf) ascending and a back run stored
 // descending from the end of the buffer, [cap-nb, cap).  Logical element i is
 // physical i for i < nf and cap-1-(i-nf) otherwise.
+constexpr uint32_t kTileStreams = 8;
+
 struct Ctrl {
     uint64_t nf[2];
     uint64_t nb[2];
@@ -49,6 +51,9 @@ struct Ctrl {
     uint64_t cnt_rx_in, cnt_rx_out, cnt_rx_launches;
     uint64_t cnt_cliff_in, cnt_cliff_launches;
     uint64_t aux[4];
+    // tile counters of the look-back kernels, one per workgroup stream
+    // (blockIdx modulo kTileStreams), each on a cache line of its own
+    alignas(128) uint32_t tile_ctr[kTileStreams][32];
 };
 
 // Tile boundary of an RX merge: the split of merged position b.

@@ -7,7 +7,7 @@ namespace orqa {
 
 constexpr int kScIn = 160;   // features per string
 constexpr int kScH = 128;    // hidden width
-constexpr int kScTile = 64;  // strings per forward tile
+constexpr int kScThreads = 512;  // forward workgroup: 8 waves sharing one copy of the weights
 // flat fp32 parameter vector: W1 (128x160) | b1 (128) | W2 (128x128) | b2 (128) | W3 (128) | b3 (1)
 constexpr int kScOffW1 = 0;
 constexpr int kScOffB1 = kScOffW1 + kScH * kScIn;
@@ -59,6 +59,7 @@ struct ScorerFwdArgs {
     float* z1_out;        // n x 128 or null
     float* z2_out;        // n x 128 or null
     uint16_t* f_out;      // n x 160 or null
+    uint64_t* counters;   // [0] strings scored, [1] launches (added by workgroup 0), or null
 };
 
 struct ScorerBwdArgs {

@@ -18,10 +18,22 @@ typedef float floatx4 __attribute__((ext_vector_type(4)));
 __device__ __forceinline__ uint16_t f2bf(float f) { return scorer_bf16(f); }  // round to nearest even
 __device__ __forceinline__ float bf2f(uint16_t b) { return __uint_as_float(static_cast<uint32_t>(b) << 16); }
 
-__device__ __forceinline__ float gelu(float x) { return 0.5f * x * (1.0f + erff(x * 0.70710678118654752f)); }
+// erf by Hastings' rational approximation (Abramowitz & Stegun, Handbook of
+// Mathematical Functions, 7.1.26): for u >= 0, erf(u) = 1 - t (a1 + t (a2 +
+// t (a3 + t (a4 + t a5)))) exp(-u^2) with t = 1 / (1 + p u), |error| <= 1.5e-7,
+// far below the bf16 rounding the activations get next.  Branch-free: one
+// exponential and one reciprocal instead of a piecewise polynomial.
+__device__ __forceinline__ float erf_as(float x) {
+    const float u = fabsf(x);
+    const float t = __frcp_rn(1.0f + 0.3275911f * u);
+    const float poly = t * (0.254829592f + t * (-0.284496736f + t * (1.421413741f + t * (-1.453152027f + t * 1.061405429f))));
+    const float e = 1.0f - poly * __expf(-u * u);
+    return copysignf(e, x);
+}
+__device__ __forceinline__ float gelu(float x) { return 0.5f * x * (1.0f + erf_as(x * 0.70710678118654752f)); }
 __device__ __forceinline__ float gelu_grad(float x) {
-    const float cdf = 0.5f * (1.0f + erff(x * 0.70710678118654752f));
-    const float pdf = 0.3989422804014327f * expf(-0.5f * x * x);
+    const float cdf = 0.5f * (1.0f + erf_as(x * 0.70710678118654752f));
+    const float pdf = 0.3989422804014327f * __expf(-0.5f * x * x);
     return cdf + x * pdf;
 }
 
@@ -29,68 +41,54 @@ __device__ __forceinline__ float gelu_grad(float x) {
 // times scale[f].  Letters: 0 X, 1 Y, 2 Z, 3 any non-identity.
 __device__ __forceinline__ float feature(const ulonglong2& mx, const ulonglong2& my, const ulonglong2& mz,
                                          const ulonglong2& ma, const ulonglong2& q, uint32_t letter, float scale) {
-    const ulonglong2 m = letter == 0 ? mx : (letter == 1 ? my : (letter == 2 ? mz : ma));
-    return scale * static_cast<float>(__popcll(m.x & q.x) + __popcll(m.y & q.y));
+    // branch-free select of the letter mask (a select chain over the four
+    // masks would be lowered to an indexed private array)
+    const uint64_t s0 = 0ull - uint64_t(letter == 0), s1 = 0ull - uint64_t(letter == 1);
+    const uint64_t s2 = 0ull - uint64_t(letter == 2), s3 = 0ull - uint64_t(letter == 3);
+    const uint64_t lo = (mx.x & s0) | (my.x & s1) | (mz.x & s2) | (ma.x & s3);
+    const uint64_t hi = (mx.y & s0) | (my.y & s1) | (mz.y & s2) | (ma.y & s3);
+    return scale * static_cast<float>(__popcll(lo & q.x) + __popcll(hi & q.y));
 }
 
-// Shared memory of the forward kernel (one workgroup per CU).
+// Shared memory of the forward kernel: the network and the feature table,
+// staged once per workgroup and read by all of its waves.
+// Weight rows are padded (160 -> 164 and 128 -> 132 bf16, i.e. 82 and 66
+// dwords) so that the 16 rows one A fragment reads fall on distinct LDS banks.
+constexpr int kW1Ld = kScIn + 4;
+constexpr int kW2Ld = kScH + 4;
 struct FwdLds {
-    alignas(16) uint16_t W1[kScH * kScIn];
-    alignas(16) uint16_t W2[kScH * kScH];
+    alignas(16) uint16_t W1[kScH * kW1Ld];
+    alignas(16) uint16_t W2[kScH * kW2Ld];
     float W3[kScH];
     float b1[kScH], b2[kScH], b3;
     ulonglong2 qmask[kScIn];
     float fscale[kScIn];
     uint8_t letter[kScIn];
-    alignas(16) uint16_t F[kScTile * kScIn];  // features, later reused for h2
-    alignas(16) uint16_t H[kScTile * kScH];   // h1
 };
 
-// One 64x128 layer: D = A (64 x K, bf16 row-major in LDS) . W^T (W: 128 x K
-// bf16 row-major).  Wave w owns output column tiles 2w, 2w+1 for all four row
-// tiles.  mfma_f32_16x16x16 bf16 operand layout: lane l holds A[l%16][4(l/16)+i],
-// B[4(l/16)+i][l%16] and D[4(l/16)+i][l%16], i = 0..3.
-template <int K>
-__device__ __forceinline__ void layer64(const uint16_t* A, const uint16_t* W, floatx4 acc[4][2]) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int r = lane & 15, kq = (lane >> 4) * 4;
-#pragma unroll
-    for (int mt = 0; mt < 4; ++mt)
-#pragma unroll
-        for (int j = 0; j < 2; ++j) acc[mt][j] = floatx4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll 2
-    for (int kt = 0; kt < K / 16; ++kt) {
-        bf16x4 b[2];
-#pragma unroll
-        for (int j = 0; j < 2; ++j) {
-            const int n = (2 * wave + j) * 16 + r;
-            b[j] = *reinterpret_cast<const bf16x4*>(W + n * K + kt * 16 + kq);
-        }
-#pragma unroll
-        for (int mt = 0; mt < 4; ++mt) {
-            const bf16x4 a = *reinterpret_cast<const bf16x4*>(A + (mt * 16 + r) * K + kt * 16 + kq);
-#pragma unroll
-            for (int j = 0; j < 2; ++j) acc[mt][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b[j], acc[mt][j], 0, 0, 0);
-        }
-    }
-}
-
-// Forward over strings [0, n) of a (virtual) key array.  Writes y (the
-// network output, log10 of the predicted weight) and, for training, z1, z2
-// (pre-activations) and the bf16 features.
-__global__ __launch_bounds__(kThreads) void k_scorer_forward(ScorerFwdArgs A) {
+// Forward over strings [0, n) of a (virtual) key array.  Each wave scores 16
+// strings at a time and computes every layer transposed, out-features x
+// strings: with the mfma_f32_16x16x16 bf16 operand layout (lane l holds
+// A[l%16][4(l/16)+i], B[4(l/16)+i][l%16], D[4(l/16)+i][l%16]) the output tile
+// of one layer is exactly the B operand of the next, so the hidden
+// activations never leave registers.  Lane l works on string l%16; its B
+// operand of layer 1 (features 4(l/16)..+3 of a 16-feature block) is computed
+// in place from the key.  Weights are the A operands, read from LDS.
+// Writes y (log10 of the predicted weight) and, for training, z1, z2 (the
+// pre-activations) and the bf16 features.
+__global__ __launch_bounds__(kScThreads) void k_scorer_forward(ScorerFwdArgs A) {
     extern __shared__ __align__(16) unsigned char smem[];
     FwdLds& L = *reinterpret_cast<FwdLds*>(smem);
     const int tid = threadIdx.x;
     const ScorerDev& S = A.net;
-    for (int i = tid; i < kScH * kScIn; i += kThreads) L.W1[i] = S.W1[i];
-    for (int i = tid; i < kScH * kScH; i += kThreads) L.W2[i] = S.W2[i];
-    for (int i = tid; i < kScH; i += kThreads) {
+    for (int i = tid; i < kScH * kScIn; i += kScThreads) L.W1[(i / kScIn) * kW1Ld + i % kScIn] = S.W1[i];
+    for (int i = tid; i < kScH * kScH; i += kScThreads) L.W2[(i / kScH) * kW2Ld + i % kScH] = S.W2[i];
+    for (int i = tid; i < kScH; i += kScThreads) {
         L.W3[i] = bf2f(S.W3[i]);
         L.b1[i] = S.b1[i];
         L.b2[i] = S.b2[i];
     }
-    for (int i = tid; i < kScIn; i += kThreads) {
+    for (int i = tid; i < kScIn; i += kScThreads) {
         L.qmask[i] = S.qmask[i];
         L.fscale[i] = S.fscale[i];
         L.letter[i] = S.letter[i];
@@ -98,84 +96,108 @@ __global__ __launch_bounds__(kThreads) void k_scorer_forward(ScorerFwdArgs A) {
     if (tid == 0) L.b3 = S.b3[0];
     const uint64_t n = A.nf_ptr ? A.nf_ptr[0] + A.nb_ptr[0] : A.n;
     const uint64_t nf = A.nf_ptr ? A.nf_ptr[0] : n;
-    const uint64_t ntiles = (n + kScTile - 1) / kScTile;
+    if (A.counters && blockIdx.x == 0 && tid == 0) {
+        atomicAdd(reinterpret_cast<unsigned long long*>(&A.counters[0]), static_cast<unsigned long long>(n));
+        atomicAdd(reinterpret_cast<unsigned long long*>(&A.counters[1]), 1ull);
+    }
     __syncthreads();
-    const int lane = tid & 63, wave = tid >> 6;
+    const int lane = tid & 63;
+    const int r = lane & 15, kq = (lane >> 4) * 4;
+    constexpr int kWaves = kScThreads / 64;
+    const uint64_t nwt = (n + 15) / 16;
 
-    for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-        // ---- features: 4 threads per string, 40 features each
-        {
-            const int s = tid >> 2, part = tid & 3;
-            const uint64_t i = tile * kScTile + s;
-            ulonglong2 x = make_ulonglong2(0, 0), z = make_ulonglong2(0, 0);
-            if (i < n) {
-                const uint64_t p = i < nf ? i : A.cap - 1 - (i - nf);
-                x = A.X[p];
-                z = A.Z[p];
-                if (A.xrot) x = rotl_n(x, A.xrot, A.nq);
+    for (uint64_t wt = uint64_t(blockIdx.x) * kWaves + (tid >> 6); wt < nwt; wt += uint64_t(gridDim.x) * kWaves) {
+        const uint64_t i = wt * 16 + r;
+        const bool live = i < n;
+        ulonglong2 x = make_ulonglong2(0, 0), z = make_ulonglong2(0, 0);
+        if (live) {
+            const uint64_t p = i < nf ? i : A.cap - 1 - (i - nf);
+            x = A.X[p];
+            z = A.Z[p];
+            if (A.xrot) x = rotl_n(x, A.xrot, A.nq);
+        }
+        const ulonglong2 mx = make_ulonglong2(x.x & ~z.x, x.y & ~z.y);
+        const ulonglong2 my = make_ulonglong2(x.x & z.x, x.y & z.y);
+        const ulonglong2 mz = make_ulonglong2(z.x & ~x.x, z.y & ~x.y);
+        const ulonglong2 ma = make_ulonglong2(x.x | z.x, x.y | z.y);
+
+        // ---- layer 1: z1^T = W1 f^T (+ b1)
+        floatx4 acc[kScH / 16];
+#pragma unroll
+        for (int mt = 0; mt < kScH / 16; ++mt) acc[mt] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 2
+        for (int kt = 0; kt < kScIn / 16; ++kt) {
+            bf16x4 b;
+            uint16_t fv[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int f = kt * 16 + kq + q;
+                fv[q] = f2bf(feature(mx, my, mz, ma, L.qmask[f], L.letter[f], L.fscale[f]));
+                b[q] = static_cast<short>(fv[q]);
             }
-            const ulonglong2 mx = make_ulonglong2(x.x & ~z.x, x.y & ~z.y);
-            const ulonglong2 my = make_ulonglong2(x.x & z.x, x.y & z.y);
-            const ulonglong2 mz = make_ulonglong2(z.x & ~x.x, z.y & ~x.y);
-            const ulonglong2 ma = make_ulonglong2(x.x | z.x, x.y | z.y);
-            for (int f = part * (kScIn / 4); f < (part + 1) * (kScIn / 4); ++f) {
-                const uint16_t v = f2bf(feature(mx, my, mz, ma, L.qmask[f], L.letter[f], L.fscale[f]));
-                L.F[s * kScIn + f] = v;
-                if (A.f_out && i < n) A.f_out[i * kScIn + f] = v;
+            if (A.f_out && live) {
+                uint2 pk;
+                pk.x = uint32_t(fv[0]) | (uint32_t(fv[1]) << 16);
+                pk.y = uint32_t(fv[2]) | (uint32_t(fv[3]) << 16);
+                *reinterpret_cast<uint2*>(A.f_out + i * kScIn + kt * 16 + kq) = pk;
+            }
+#pragma unroll
+            for (int mt = 0; mt < kScH / 16; ++mt) {
+                const bf16x4 a = *reinterpret_cast<const bf16x4*>(L.W1 + (mt * 16 + r) * kW1Ld + kt * 16 + kq);
+                acc[mt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[mt], 0, 0, 0);
             }
         }
-        __syncthreads();
-
-        // ---- layer 1: z1 = F W1^T + b1, h1 = gelu(z1)
-        floatx4 acc[4][2];
-        layer64<kScIn>(L.F, L.W1, acc);
+        // h1 = gelu(z1) in bf16: already laid out as layer 2's B operand
+        bf16x4 h1[kScH / 16];
 #pragma unroll
-        for (int mt = 0; mt < 4; ++mt)
+        for (int mt = 0; mt < kScH / 16; ++mt) {
+            float zz[4];
 #pragma unroll
-            for (int j = 0; j < 2; ++j) {
-                const int col = (2 * wave + j) * 16 + (lane & 15);
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const int row = mt * 16 + (lane >> 4) * 4 + q;
-                    const float zz = acc[mt][j][q] + L.b1[col];
-                    L.H[row * kScH + col] = f2bf(gelu(zz));
-                    const uint64_t i = tile * kScTile + row;
-                    if (A.z1_out && i < n) A.z1_out[i * kScH + col] = zz;
-                }
+            for (int q = 0; q < 4; ++q) {
+                zz[q] = acc[mt][q] + L.b1[mt * 16 + kq + q];
+                h1[mt][q] = static_cast<short>(f2bf(gelu(zz[q])));
             }
-        __syncthreads();
-
-        // ---- layer 2: z2 = h1 W2^T + b2, h2 = gelu(z2) (into the feature buffer)
-        layer64<kScH>(L.H, L.W2, acc);
-        __syncthreads();  // every wave is done reading F before h2 overwrites it
-#pragma unroll
-        for (int mt = 0; mt < 4; ++mt)
-#pragma unroll
-            for (int j = 0; j < 2; ++j) {
-                const int col = (2 * wave + j) * 16 + (lane & 15);
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const int row = mt * 16 + (lane >> 4) * 4 + q;
-                    const float zz = acc[mt][j][q] + L.b2[col];
-                    L.F[row * kScH + col] = f2bf(gelu(zz));
-                    const uint64_t i = tile * kScTile + row;
-                    if (A.z2_out && i < n) A.z2_out[i * kScH + col] = zz;
-                }
-            }
-        __syncthreads();
-
-        // ---- layer 3: y = h2 . W3 + b3 (4 threads per string, fp32)
-        {
-            const int s = tid >> 2, part = tid & 3;
-            float acc3 = 0.f;
-            for (int k = part * (kScH / 4); k < (part + 1) * (kScH / 4); ++k)
-                acc3 += bf2f(L.F[s * kScH + k]) * L.W3[k];
-            acc3 += __shfl_xor(acc3, 1, 64);
-            acc3 += __shfl_xor(acc3, 2, 64);
-            const uint64_t i = tile * kScTile + s;
-            if (part == 0 && i < n) A.y_out[i] = acc3 + L.b3;
+            if (A.z1_out && live)
+                *reinterpret_cast<float4*>(A.z1_out + i * kScH + mt * 16 + kq) = make_float4(zz[0], zz[1], zz[2], zz[3]);
         }
-        __syncthreads();
+
+        // ---- layers 2 and 3: z2^T = W2 h1^T (+ b2), then y = W3 . bf16(gelu(z2))
+        // + b3 in fp32.  Two output tiles at a time keep the register count low;
+        // the four lanes of a string hold disjoint feature sets and are summed
+        // by two shuffles.
+        float y = 0.f;
+#pragma unroll
+        for (int mt = 0; mt < kScH / 16; mt += 2) {
+            floatx4 c0 = floatx4{0.f, 0.f, 0.f, 0.f}, c1 = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int kt = 0; kt < kScH / 16; ++kt) {  // static: h1[kt] is a register
+                const bf16x4 a0 = *reinterpret_cast<const bf16x4*>(L.W2 + (mt * 16 + r) * kW2Ld + kt * 16 + kq);
+                const bf16x4 a1 = *reinterpret_cast<const bf16x4*>(L.W2 + (mt * 16 + 16 + r) * kW2Ld + kt * 16 + kq);
+                c0 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a0, h1[kt], c0, 0, 0, 0);
+                c1 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a1, h1[kt], c1, 0, 0, 0);
+            }
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const floatx4& c = h ? c1 : c0;
+                const int m = mt + h;
+                float zz[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int k = m * 16 + kq + q;
+                    zz[q] = c[q] + L.b2[k];
+                    y += bf2f(f2bf(gelu(zz[q]))) * L.W3[k];
+                }
+                if (A.z2_out && live)
+                    *reinterpret_cast<float4*>(A.z2_out + i * kScH + m * 16 + kq) =
+                        make_float4(zz[0], zz[1], zz[2], zz[3]);
+            }
+            // keep the scheduler from hoisting the next tiles' weight loads
+            // (it would otherwise hold all 64 fragments in registers and spill)
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        y += __shfl_xor(y, 16, 64);
+        y += __shfl_xor(y, 32, 64);
+        if (lane < 16 && live) A.y_out[i] = y + L.b3;
     }
 }
 
@@ -287,7 +309,7 @@ hipError_t launch_scorer_forward(const ScorerFwdArgs& a, hipStream_t s, int grid
         if (e != hipSuccess) return e;
         attr = true;
     }
-    k_scorer_forward<<<dim3(grid), dim3(kThreads), sizeof(FwdLds), s>>>(a);
+    k_scorer_forward<<<dim3(grid), dim3(kScThreads), sizeof(FwdLds), s>>>(a);
     return hipGetLastError();
 }
 

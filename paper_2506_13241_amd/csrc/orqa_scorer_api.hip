@@ -77,7 +77,7 @@ struct ps_scorer {
     float* dz2 = nullptr;
     uint16_t* f = nullptr;
     double* loss = nullptr;
-    int grid = 256;
+    int grid = 512;
 };
 
 namespace {
