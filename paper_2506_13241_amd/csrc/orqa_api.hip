@@ -216,7 +216,9 @@ bool alloc_aux(ps_handle* h, size_t cap, bool with_score, Aux* a) {
     const uint64_t mt = cap / kRxTile + 4;
     const uint64_t st_tiles = cap / kCompactTile + 4;
     const uint64_t sort_tiles = cap / kSortTile + 4;
-    const size_t words = std::max<size_t>(2 * std::max(mt, st_tiles), 256 * sort_tiles);
+    const uint64_t tiles = std::max(mt, st_tiles);
+    // per channel: one word per tile, then one per group of 64 tiles (RX merge)
+    const size_t words = std::max<size_t>(2 * tiles + 2 * (tiles / 64 + 2), 256 * sort_tiles);
     bool ok = grab(reinterpret_cast<void**>(&a->rank[0]), cap * sizeof(uint32_t)) &&
               grab(reinterpret_cast<void**>(&a->rank[1]), cap * sizeof(uint32_t)) &&
               grab(reinterpret_cast<void**>(&a->desc), (mt + 2) * sizeof(TileDesc)) &&

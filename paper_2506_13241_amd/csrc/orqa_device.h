@@ -193,6 +193,128 @@ __device__ __forceinline__ uint64_t lookback_wave(uint64_t* st, uint64_t stride,
     return excl;
 }
 
+// Two-level decoupled look-back.  Tiles form groups of 64; the last tile of
+// a group also publishes the group's aggregate (before its own look-back) and
+// the group's inclusive prefix (after it) in gst[group].  A tile sums the
+// tiles of its own group that precede it, then walks back over groups, 64
+// groups (4096 tiles) per round trip: the inclusive prefixes no longer have to
+// creep forward 64 tiles per round trip.  Must be called by all 64 lanes of
+// one wave; returns the exclusive prefix of `tile` (uniform).  Every wait is
+// on tiles or groups that took their indices earlier, and a group's aggregate
+// is formed by its last tile from aggregates that are published without
+// waiting, so every wait ends.
+__device__ __forceinline__ uint64_t lookback_wave2(uint64_t* st, uint64_t* gst, uint32_t tile, uint32_t ep,
+                                                   uint64_t agg, uint32_t* err) {
+    const int lane = lane_id();
+    const uint32_t grp = tile >> 6, first = grp << 6;
+    const bool last_in_group = (tile & 63u) == 63u;
+    if (tile == 0) {
+        if (lane == 0) st_rel(st, st_pack(ep, 2, agg));
+        return 0;
+    }
+    if (lane == 0) st_rel(st + tile, st_pack(ep, 1, agg));
+    const uint64_t t0 = wall_clock64();
+    bool timed_out = false;
+    // The last tile of a group publishes the group's status first: scanning
+    // the group from its end (lane 0 = this tile), the words up to the first
+    // inclusive prefix give the group's inclusive prefix; with none, all 64
+    // aggregates give the group aggregate.  (A tile's word may already hold
+    // its inclusive prefix instead of its aggregate, so the scan stops there.)
+    if (last_in_group) {
+        uint64_t v;
+        int fi = 64;
+        while (true) {
+            v = ld_acq(st + tile - lane);
+            const uint32_t fl = st_flag(v, ep);
+            const uint64_t incl = __ballot(fl == 2u);
+            const uint64_t pend = __ballot(fl == 0u);
+            fi = incl ? (__ffsll(static_cast<unsigned long long>(incl)) - 1) : 64;
+            const int fr = pend ? (__ffsll(static_cast<unsigned long long>(pend)) - 1) : 64;
+            if (fr > fi || fr == 64) break;
+            if (__any(wall_clock64() - t0 > kLookbackTicks)) {
+                timed_out = true;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(16);
+        }
+        const uint64_t gsum = wave_sum_u64((!timed_out && lane <= fi) ? (v & kValMask) : 0ull);
+        if (lane == 0 && !timed_out) st_rel(gst + grp, st_pack(ep, fi < 64 ? 2u : 1u, gsum));
+    }
+    uint64_t excl = 0;
+    bool done = false;
+    // ---- within the group: tiles first .. tile-1, nearest first
+    if (!timed_out && tile > first) {
+        const int64_t j = int64_t(tile) - 1 - lane;
+        const bool in = j >= int64_t(first);
+        uint64_t v = 0;
+        int fi = 64;
+        while (true) {
+            uint32_t fl = 1;  // lanes outside the group: ready, value 0
+            v = 0;
+            if (in) {
+                v = ld_acq(st + j);
+                fl = st_flag(v, ep);
+            }
+            const uint64_t incl = __ballot(in && fl == 2u);
+            const uint64_t pend = __ballot(fl == 0u);
+            fi = incl ? (__ffsll(static_cast<unsigned long long>(incl)) - 1) : 64;
+            const int fr = pend ? (__ffsll(static_cast<unsigned long long>(pend)) - 1) : 64;
+            if (fr > fi || fr == 64) break;
+            if (__any(wall_clock64() - t0 > kLookbackTicks)) {
+                timed_out = true;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(16);
+        }
+        if (!timed_out) {
+            excl += wave_sum_u64((in && lane <= fi) ? (v & kValMask) : 0ull);
+            done = fi < 64;
+        }
+    }
+    // ---- earlier groups, 64 per round trip (group 0 always publishes an
+    // inclusive prefix: its scan reaches tile 0, which is inclusive at once)
+    if (!timed_out && !done && grp > 0) {
+        int64_t base = int64_t(grp) - 1;
+        while (true) {
+            const int64_t g = base - lane;
+            uint64_t v = 0;
+            int fi = 64;
+            uint64_t incl = 0;
+            while (true) {
+                uint32_t fl = 2;  // before group 0: inclusive 0
+                v = 0;
+                if (g >= 0) {
+                    v = ld_acq(gst + g);
+                    fl = st_flag(v, ep);
+                }
+                incl = __ballot(fl == 2u);
+                const uint64_t pend = __ballot(fl == 0u);
+                fi = incl ? (__ffsll(static_cast<unsigned long long>(incl)) - 1) : 64;
+                const int fr = pend ? (__ffsll(static_cast<unsigned long long>(pend)) - 1) : 64;
+                if (fr > fi || fr == 64) break;
+                if (__any(wall_clock64() - t0 > kLookbackTicks)) {
+                    timed_out = true;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(16);
+            }
+            if (timed_out) break;
+            excl += wave_sum_u64(lane <= fi ? (v & kValMask) : 0ull);
+            if (incl) break;
+            base -= 64;
+        }
+    }
+    if (timed_out) {
+        if (lane == 0) atomicOr(err, kErrLookback);
+        excl = 0;
+    }
+    if (lane == 0) {
+        st_rel(st + tile, st_pack(ep, 2, excl + agg));
+        if (last_in_group) st_rel(gst + grp, st_pack(ep, 2, excl + agg));
+    }
+    return excl;
+}
+
 // Single-thread look-back (one channel per thread, used by the radix sort with
 // one thread per digit).
 __device__ __forceinline__ uint64_t lookback_thread(uint64_t* st, uint64_t stride, uint32_t tile, uint32_t ep, uint64_t agg,

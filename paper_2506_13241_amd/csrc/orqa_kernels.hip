@@ -386,12 +386,12 @@ __global__ __launch_bounds__(kThreads) void k_rx_merge(RxArgs A, GateTrig g) {
         }
 
         // ---- tile bases: wave 0 front run, wave 1 back run
-        if (wave == 0) {
-            const uint64_t b = lookback_wave(A.status, 1, tile, ep, totA, &ctrl->err);
-            if (lane_id() == 0) sBase[0] = b;
-        } else if (wave == 1) {
-            const uint64_t b = lookback_wave(A.status + A.max_tiles, 1, tile, ep, totB, &ctrl->err);
-            if (lane_id() == 0) sBase[1] = b;
+        if (wave < 2) {  // wave 0: front run, wave 1: back run (two-level look-back)
+            const uint64_t gmax = A.max_tiles / 64 + 2;
+            uint64_t* st = A.status + wave * A.max_tiles;
+            uint64_t* gst = A.status + 2 * A.max_tiles + wave * gmax;
+            const uint64_t b = lookback_wave2(st, gst, tile, ep, wave ? totB : totA, &ctrl->err);
+            if (lane_id() == 0) sBase[wave] = b;
         }
         __syncthreads();
         const uint64_t baseA = sBase[0], baseB = sBase[1];
