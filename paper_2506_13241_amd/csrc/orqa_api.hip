@@ -583,6 +583,37 @@ int sort_by_rank_z(ps_handle* h, int b, int* result) {
     const uint64_t n = c.nf[b];
     *result = b;
     if (n <= 1) return PS_OK;
+    {  // every x-group small enough: one pass sorts each group inside a workgroup
+        GroupSortArgs g{};
+        g.ctrl = h->ctrl;
+        g.in_buf = b;
+        g.out_buf = 1 - b;
+        g.Xs = h->buf[b].X;
+        g.Zs = h->buf[b].Z;
+        g.Cs = h->buf[b].C;
+        g.Xd = h->buf[1 - b].X;
+        g.Zd = h->buf[1 - b].Z;
+        g.Cd = h->buf[1 - b].C;
+        size_t slot;
+        rc = ev_begin(h, 2, &slot);
+        if (rc) return rc;
+        HIP_TRY(launch_group_sort(g, h->dtype, h->LP, h->stream, h->grid / 2));
+        rc = ev_end(h, slot);
+        if (rc) return rc;
+        Ctrl c2;
+        rc = read_ctrl(h, &c2);
+        if (rc) return rc;
+        h->sort_passes += 1;
+        h->sort_elems += double(n);
+        if (c2.aux[2] == 0) {
+            *result = 1 - b;
+            return PS_OK;
+        }
+        // a group too large for one workgroup: radix sort from the untouched input
+        const uint64_t zero = 0;
+        HIP_TRY(hipMemcpyAsync(&h->ctrl->aux[2], &zero, 8, hipMemcpyHostToDevice, h->stream));
+        HIP_TRY(hipMemcpyAsync(&h->ctrl->nf[1 - b], &zero, 8, hipMemcpyHostToDevice, h->stream));
+    }
     HIP_TRY(hipMemsetAsync(h->hist, 0, kSortDigits * 256 * sizeof(uint32_t), h->stream));
     HIP_TRY(launch_sort_hist(h->ctrl, b, h->rank[b], h->buf[b].Z, h->hist, h->stream, h->grid));
     std::vector<uint32_t> hist(kSortDigits * 256);

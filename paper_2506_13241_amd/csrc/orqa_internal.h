@@ -149,6 +149,25 @@ hipError_t launch_compact(const CompactArgs& a, int dtype, int lp, hipStream_t s
 hipError_t launch_sort_hist(Ctrl* ctrl, int buf, const uint32_t* R, const ulonglong2* Z, uint32_t* hist,
                             hipStream_t s, int grid);
 hipError_t launch_sort_pass(const SortPassArgs& a, int dtype, int lp, hipStream_t s, int grid);
+
+// Re-sort after a Clifford layer when every x-group is small: each group is
+// sorted by z inside one workgroup, in place of the groups' positions.
+constexpr int kGsThreads = 512;
+constexpr int kGsTile = 1024;                  // positions whose groups a workgroup sorts
+constexpr int kGsMaxGroup = 2048;              // larger groups: radix-sort fallback
+constexpr int kGsCap = kGsTile + kGsMaxGroup;  // strings staged per tile
+constexpr int kGsIPT = kGsCap / kGsThreads;
+struct GroupSortArgs {
+    Ctrl* ctrl;
+    int in_buf, out_buf;
+    const ulonglong2* Xs;
+    const ulonglong2* Zs;
+    const void* Cs;
+    ulonglong2* Xd;
+    ulonglong2* Zd;
+    void* Cd;
+};
+hipError_t launch_group_sort(const GroupSortArgs& a, int dtype, int lp, hipStream_t s, int grid);
 hipError_t launch_reduce(Ctrl* ctrl, int buf, const ulonglong2* X, const void* C, uint64_t cap, int mode,
                          double* partial, double* out, int dtype, int lp, int lanes, hipStream_t s);
 hipError_t launch_fill_u64(uint64_t* p, uint64_t v, size_t n, hipStream_t s);

@@ -853,6 +853,119 @@ hipError_t launch_sort_hist(Ctrl* ctrl, int buf, const uint32_t* R, const ulongl
     return hipGetLastError();
 }
 
+// ================================================================ group sort
+// After the Clifford layer the operator is still ordered by x-group; only the
+// z order inside each group is lost (every z of a group was XORed with the
+// same mask).  When no group exceeds kGsMaxGroup strings, each group is
+// sorted by z inside one workgroup: a string's new position is its group's
+// start plus the number of group members with a smaller z (z values within a
+// group are distinct).  Groups keep their positions, so no prefix sum across
+// workgroups is needed.  Workgroup tiles cover kGsTile positions and own the
+// groups that start there.  A group that would not fit sets ctrl->aux[2] and
+// the caller falls back to the radix sort (the input is left untouched).
+template <typename CT, int LP>
+__global__ __launch_bounds__(kGsThreads) void k_group_sort(GroupSortArgs A) {
+    __shared__ ulonglong2 sZ[kGsCap];
+    __shared__ uint8_t sF[kGsCap + 1];  // group-start flags, sF[m] = 1 as a sentinel
+    __shared__ uint32_t sA, sB;
+    Ctrl* ctrl = A.ctrl;
+    const CT* __restrict__ Cs = static_cast<const CT*>(A.Cs);
+    CT* __restrict__ Cd = static_cast<CT*>(A.Cd);
+    const int tid = threadIdx.x;
+    const uint64_t n = ctrl->nf[A.in_buf];
+    const uint64_t ntiles = ctrl->err ? 0 : (n + kGsTile - 1) / kGsTile;
+    if (blockIdx.x == 0 && tid == 0 && ctrl->err == 0u) {
+        ctrl->nf[A.out_buf] = n;
+        ctrl->nb[A.out_buf] = 0;
+    }
+    for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const uint64_t t0 = tile * kGsTile;
+        const uint64_t t1 = t0 + kGsTile < n ? t0 + kGsTile : n;
+        if (tid == 0) {
+            sA = 0xFFFFFFFFu;
+            sB = 0xFFFFFFFFu;
+        }
+        __syncthreads();
+        // first group start at or after t0 (a) and at or after t1 (b)
+        for (int i = tid; i < kGsMaxGroup; i += kGsThreads) {
+            const uint64_t p = t0 + i, q = t1 + i;
+            if (p < n && (p == 0 || !k_eq(A.Xs[p], A.Xs[p - 1]))) atomicMin(&sA, uint32_t(i));
+            if (q < n && !k_eq(A.Xs[q], A.Xs[q - 1])) atomicMin(&sB, uint32_t(i));
+        }
+        __syncthreads();
+        // A search window of full length without a group start means a group
+        // longer than kGsMaxGroup; one cut short by the end of the operator
+        // only means that no group starts there.
+        const bool full_a = t0 + kGsMaxGroup <= n, full_b = t1 + kGsMaxGroup <= n;
+        const bool over = (sA == 0xFFFFFFFFu && full_a) || (t1 < n && sB == 0xFFFFFFFFu && full_b);
+        if (over) {
+            if (tid == 0) atomicOr(reinterpret_cast<unsigned int*>(&ctrl->aux[2]), 1u);
+            __syncthreads();
+            continue;
+        }
+        const uint64_t a = sA == 0xFFFFFFFFu ? n : t0 + sA;
+        const uint64_t b = (t1 < n && sB != 0xFFFFFFFFu) ? t1 + sB : n;
+        if (a >= t1) {  // no group starts here: the tile's strings belong to an earlier tile's group
+            __syncthreads();
+            continue;
+        }
+        const uint32_t m = uint32_t(b - a);  // <= kGsCap by construction
+        // stage z and the group-start flags; keep x and coefficients in registers
+        constexpr bool kRegC = LP * sizeof(CT) <= 16;  // wider rows are copied at write time
+        ulonglong2 xr[kGsIPT], zr[kGsIPT];
+        CT cr[kGsIPT][kRegC ? LP : 1];
+#pragma unroll
+        for (int k = 0; k < kGsIPT; ++k) {
+            const uint32_t e = k * kGsThreads + tid;
+            const uint64_t p = a + (e < m ? e : 0u);
+            xr[k] = A.Xs[p];
+            zr[k] = A.Zs[p];
+            if constexpr (kRegC) {
+#pragma unroll
+                for (int l = 0; l < LP; ++l) cr[k][l] = Cs[p * LP + l];
+            }
+            if (e < m) {
+                sZ[e] = zr[k];
+                sF[e] = uint8_t(e == 0 || !k_eq(xr[k], A.Xs[p - 1]));
+            }
+        }
+        if (tid == 0) sF[m] = 1;
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < kGsIPT; ++k) {
+            const uint32_t e = k * kGsThreads + tid;
+            if (e >= m) continue;
+            const ulonglong2 z = zr[k];
+            uint32_t r = 0, j = e;
+            while (!sF[j]) {  // members before e in the group
+                --j;
+                r += k_lt(sZ[j], z);
+            }
+            const uint32_t gs = j;
+            for (j = e + 1; !sF[j]; ++j) r += k_lt(sZ[j], z);  // members after e
+            const uint64_t d = a + gs + r;
+            A.Xd[d] = xr[k];
+            A.Zd[d] = z;
+            if constexpr (kRegC) {
+#pragma unroll
+                for (int l = 0; l < LP; ++l) Cd[d * LP + l] = cr[k][l];
+            } else {
+                const uint64_t p = a + e;
+#pragma unroll 4
+                for (int l = 0; l < LP; ++l) Cd[d * LP + l] = Cs[p * LP + l];
+            }
+        }
+        __syncthreads();
+    }
+}
+
+hipError_t launch_group_sort(const GroupSortArgs& a, int dtype, int lp, hipStream_t s, int grid) {
+#define L_GS(T, L) k_group_sort<T, L><<<dim3(grid), dim3(kGsThreads), 0, s>>>(a)
+    ORQA_DISPATCH(dtype, lp, L_GS);
+#undef L_GS
+    return hipGetLastError();
+}
+
 hipError_t launch_sort_pass(const SortPassArgs& a, int dtype, int lp, hipStream_t s, int grid) {
 #define L_SP(T, L) k_sort_pass<T, L><<<dim3(grid), dim3(kThreads), 0, s>>>(a)
     ORQA_DISPATCH(dtype, lp, L_SP);

@@ -214,3 +214,37 @@ def test_determinism_bit_identical():
         res.append((k, c, g.expectation_z()[0]))
     assert np.array_equal(res[0][0], res[1][0]) and np.array_equal(res[0][1], res[1][1])
     assert res[0][2] == res[1][2]
+
+
+def test_clifford_resort_group_sort_and_radix_fallback():
+    """The re-sort after a Clifford layer sorts each x-group inside one
+    workgroup when no group exceeds 2048 strings, and falls back to the radix
+    sort otherwise.  Both cases against the oracle, bit for bit: a set of many
+    small groups, and the same set plus one x-group of 6000 strings."""
+    import paper_2506_13241_amd as P
+    n = 127
+    lat = w.eagle_127()
+    zz = w.kicked_ising_step(lat, 0.8)[0]
+    terms, coeffs = w.random_pauli_set(n, 30000, seed=21, support=w.ball(lat, 62, 4))
+    # one big x-group: 6000 strings sharing the x mask of terms[0], random z on the ball
+    zs, _ = w.random_pauli_set(n, 8000, seed=22, support=w.ball(lat, 62, 4))
+    big = np.repeat(terms[:1], len(zs), axis=0)
+    big[:, 2:] = zs[:, 2:]
+    big = np.unique(big, axis=0)[:6000]
+    bc = np.linspace(0.1, 1.0, len(big))[:, None]
+    for label, tt, cc in (("small groups", terms, coeffs),
+                          ("one group of 6000", np.concatenate([terms, big]), np.concatenate([coeffs, bc]))):
+        tt, idx = np.unique(tt, axis=0, return_index=True)
+        cc = cc[idx]
+        say(f"resort: {label}, {len(tt)} strings")
+        g = gpu_sum(n, tt, cc)
+        o = OracleSum(n, tt, cc)
+        g.stats(reset=True)
+        g.apply_rotation_layer(zz)
+        o.apply(zz)
+        assert_same_operator(g, o, coeff_exact=True)
+        passes = g.stats()["sort_passes"]
+        if label == "small groups":
+            assert passes == 1
+        else:
+            assert passes > 1
