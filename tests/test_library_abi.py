@@ -57,3 +57,32 @@ def test_invalid_arguments_fail_before_any_device_call(lib):
     assert L.pauli_sum_create(0, 1, 0, 0, None, None, 0, None, ctypes.byref(h)) == P.PS_ERR_INVALID
     assert L.pauli_sum_create(5, 33, 0, 0, None, None, 0, None, ctypes.byref(h)) == P.PS_ERR_INVALID
     assert b"n_lanes" in L.ps_last_error()
+
+
+def test_scorer_and_graph_entry_points_validate_before_device_calls(lib):
+    import numpy as np
+    import paper_2506_13241_amd as P
+    L = P.load_library()
+    s = ctypes.c_void_p()
+    qm = np.zeros((160, 2), dtype=np.uint64)
+    let = np.zeros(160, dtype=np.uint8)
+    sc = np.ones(160, dtype=np.float32)
+    ptr = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+    # NULL tables, qubit count out of range, letter out of range
+    assert L.ps_scorer_create(127, None, ptr(let), ptr(sc), None, ctypes.byref(s)) == P.PS_ERR_INVALID
+    assert L.ps_scorer_create(0, ptr(qm), ptr(let), ptr(sc), None, ctypes.byref(s)) == P.PS_ERR_INVALID
+    bad = let.copy()
+    bad[7] = 4
+    assert L.ps_scorer_create(127, ptr(qm), ptr(bad), ptr(sc), None, ctypes.byref(s)) == P.PS_ERR_INVALID
+    assert b"feature 7" in L.ps_last_error()
+    # NULL handles
+    assert L.ps_scorer_set_params(None, None, 0) == P.PS_ERR_INVALID
+    assert L.ps_scorer_get_params(None, None, 0) == P.PS_ERR_INVALID
+    assert L.ps_scorer_set_data(None, None, None, 0) == P.PS_ERR_INVALID
+    assert L.ps_scorer_forward(None, None, None) == P.PS_ERR_INVALID
+    assert L.ps_scorer_loss_grad(None, None, None) == P.PS_ERR_INVALID
+    assert L.ps_scorer_adam_step(None, ctypes.c_float(1e-3)) == P.PS_ERR_INVALID
+    assert L.ps_scorer_destroy(None) == P.PS_OK
+    assert L.pauli_sum_load_scorer(None, None) == P.PS_ERR_INVALID
+    assert L.pauli_sum_set_graphs(None, 1) == P.PS_ERR_INVALID
+    assert L.pauli_sum_set_timing(None, 1) == P.PS_ERR_INVALID
