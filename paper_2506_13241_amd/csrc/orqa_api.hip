@@ -99,13 +99,14 @@ U128 rotr_host(U128 v, int r, int n) {
 }
 U128 rotl_host(U128 v, int r, int n) { return rotr_host(v, (n - (r % n)) % n, n); }
 
-enum StageKind { ST_RX = 0, ST_CLIFF = 1 };
+enum StageKind { ST_RX = 0, ST_CLIFF = 1, ST_GEN = 2 };
 
 struct Stage {
     StageKind kind;
     size_t gate_first, gate_count;  // gates of the layer covered by this stage
-    GateTrig trig;                  // RX
+    GateTrig trig;                  // RX, general
     int qubit;                      // RX
+    ps_pauli gen;                   // general
     std::vector<CliffGen> gens;     // Clifford run
     bool needs_sort;
 };
@@ -511,6 +512,54 @@ int enqueue_rx(ps_handle* h, int in, int out, int mx_in, int mx_out, double eps_
     return ev_end(h, slot);
 }
 
+GenArgs gen_args(ps_handle* h, int in, int out, int mx_in, int mx_out) {
+    GenArgs a{};
+    a.ctrl = h->ctrl;
+    a.in_buf = in;
+    a.out_buf = out;
+    a.mx_in = mx_in;
+    a.mx_out = mx_out;
+    a.Xin = h->buf[in].X;
+    a.Zin = h->buf[in].Z;
+    a.Cin = h->buf[in].C;
+    a.Xout = h->buf[out].X;
+    a.Zout = h->buf[out].Z;
+    a.Cout = h->buf[out].C;
+    a.cap = h->cap;
+    a.status = h->status;
+    a.max_tiles = h->max_tiles;
+    a.nq = h->nq;
+    return a;
+}
+
+// General gate, first half: parents and children of every string, unsorted,
+// in true x (the stored rotation is undone).
+int enqueue_gen_branch(ps_handle* h, int in, int out, int mx_in, double eps_in, const Stage& st) {
+    GenArgs a = gen_args(h, in, out, mx_in, 1 - mx_in);
+    a.eps_in = eps_in;
+    a.xrot = h->xrot;
+    a.xj0 = st.gen.x[0];
+    a.xj1 = st.gen.x[1];
+    a.zj0 = st.gen.z[0];
+    a.zj1 = st.gen.z[1];
+    size_t slot;
+    int rc = ev_begin(h, 1, &slot);
+    if (rc) return rc;
+    HIP_TRY(launch_gen_branch(a, st.trig, h->dtype, h->LP, h->stream, h->grid));
+    return ev_end(h, slot);
+}
+
+// General gate, second half: merge the sorted entries of buffer `in` into
+// `out`, with the max of the result in slot mx_out.
+int enqueue_gen_reduce(ps_handle* h, int in, int out, int mx_out) {
+    GenArgs a = gen_args(h, in, out, 1 - mx_out, mx_out);
+    size_t slot;
+    int rc = ev_begin(h, 1, &slot);
+    if (rc) return rc;
+    HIP_TRY(launch_gen_reduce(a, h->dtype, h->LP, h->stream, h->grid));
+    return ev_end(h, slot);
+}
+
 void drop_graphs(ps_handle* h) {
     for (auto& e : h->graph_cache) (void)hipGraphExecDestroy(e.exec);
     h->graph_cache.clear();
@@ -575,7 +624,7 @@ int run_rx_graph(ps_handle* h, const std::vector<GateTrig>& trigs, double pend0,
 
 // Re-sort buffer `b` (front only, with group ranks) by (rank, z).  Returns the
 // buffer holding the result in *result.
-int sort_by_rank_z(ps_handle* h, int b, int* result) {
+int sort_by_rank_z(ps_handle* h, int b, int* result, bool full_key = false) {
     Ctrl c;
     int rc = read_ctrl(h, &c);
     if (rc) return rc;
@@ -583,7 +632,7 @@ int sort_by_rank_z(ps_handle* h, int b, int* result) {
     const uint64_t n = c.nf[b];
     *result = b;
     if (n <= 1) return PS_OK;
-    {  // every x-group small enough: one pass sorts each group inside a workgroup
+    if (!full_key) {  // every x-group small enough: one pass sorts each group inside a workgroup
         GroupSortArgs g{};
         g.ctrl = h->ctrl;
         g.in_buf = b;
@@ -615,13 +664,16 @@ int sort_by_rank_z(ps_handle* h, int b, int* result) {
         HIP_TRY(hipMemcpyAsync(&h->ctrl->nf[1 - b], &zero, 8, hipMemcpyHostToDevice, h->stream));
     }
     HIP_TRY(hipMemsetAsync(h->hist, 0, kSortDigits * 256 * sizeof(uint32_t), h->stream));
-    HIP_TRY(launch_sort_hist(h->ctrl, b, h->rank[b], h->buf[b].Z, h->hist, h->stream, h->grid));
+    HIP_TRY(launch_sort_hist(h->ctrl, b, h->rank[b], h->buf[b].Z, h->buf[b].X, full_key ? 1 : 0, h->hist, h->stream,
+                             h->grid));
     std::vector<uint32_t> hist(kSortDigits * 256);
     HIP_TRY(hipMemcpyAsync(hist.data(), h->hist, hist.size() * sizeof(uint32_t), hipMemcpyDeviceToHost, h->stream));
     HIP_TRY(hipStreamSynchronize(h->stream));
     std::vector<int> digits;
     for (int d = 0; d < kSortDigits; ++d) {
         if (d < 16 && 8 * (d & 7) + 64 * (d >> 3) >= h->nq) continue;  // z byte above the register
+        if (full_key ? (d >= 16 && d < 20) : d >= 20) continue;        // (x, z) or (rank, z)
+        if (d >= 20 && 8 * ((d - 20) & 7) + 64 * ((d - 20) >> 3) >= h->nq) continue;  // x byte above
         int nonzero = 0;
         for (int k = 0; k < 256; ++k) nonzero += hist[d * 256 + k] != 0;
         if (nonzero > 1) digits.push_back(d);
@@ -966,10 +1018,29 @@ int apply_rotation_layer(ps_handle* h, const ps_pauli* gens, const double* theta
                 continue;
             }
         }
-        return fail(PS_ERR_UNSUPPORTED,
-                    "gate %zu: only Z-only Clifford runs and sigma_x rotations on consecutive qubits "
-                    "(expected qubit %d) are built",
-                    g, xrot % h->nq);
+        {  // any other Pauli rotation: branch, full sort, merge
+            Stage s{};
+            s.kind = ST_GEN;
+            s.gate_first = g;
+            s.gate_count = 1;
+            s.gen = G;
+            GateTrig& t = s.trig;
+            std::memset(&t, 0, sizeof t);
+            bool any_c = false, any_s = false;
+            for (int a = 0; a < h->L; ++a) {
+                t.cs[a] = cs[a];
+                t.sn[a] = sn[a];
+                split_f32(cs[a], &t.cs_hi[a], &t.cs_lo[a]);
+                split_f32(sn[a], &t.sn_hi[a], &t.sn_lo[a]);
+                any_c |= cs[a] != 0.0;
+                any_s |= sn[a] != 0.0;
+            }
+            t.any_c = any_c;
+            t.any_s = any_s;
+            stages.push_back(s);
+            xrot = 0;  // the general stage leaves x unrotated
+            ++g;
+        }
     }
 
     // ---- execute.  Stages are enqueued back to back; the host synchronises
@@ -992,7 +1063,7 @@ int apply_rotation_layer(ps_handle* h, const ps_pauli* gens, const double* theta
     size_t si = 0;
     while (si < stages.size()) {
         std::vector<Launched> launched;
-        bool sort_after = false;
+        bool sort_after = false, gen_after = false;
         for (; si < stages.size(); ++si) {
             Stage& s = stages[si];
             const bool noop = s.kind == ST_CLIFF && s.gens.empty() && !(h->pend > 0.0) && !(eps_learned > 0.0);
@@ -1020,6 +1091,16 @@ int apply_rotation_layer(ps_handle* h, const ps_pauli* gens, const double* theta
             }
             launched.push_back({si, h->cur, h->mx, h->xrot, h->pend});
             const int in = h->cur, out = 1 - h->cur, mx_in = h->mx, mx_out = 1 - h->mx;
+            if (s.kind == ST_GEN) {  // branch now; sort and merge after the synchronisation
+                rc = enqueue_gen_branch(h, in, out, mx_in, h->pend, s);
+                if (rc) return rc;
+                h->cur = out;
+                h->xrot = 0;
+                h->pend = -1.0;
+                gen_after = true;
+                ++si;
+                break;
+            }
             if (s.kind == ST_RX) {
                 rc = enqueue_rx(h, in, out, mx_in, mx_out, h->pend, s.trig);
                 if (rc) return rc;
@@ -1079,6 +1160,22 @@ int apply_rotation_layer(ps_handle* h, const ps_pauli* gens, const double* theta
             h->cur = res;
             rc = check_no_error(h, "re-sort");
             if (rc) return rc;
+        }
+        if (gen_after) {  // general gate: sort the branch output by (x, z), merge equal keys
+            const int mx_branch = h->mx;  // zeroed by the branch; the merge's max goes to the other slot
+            int res = h->cur;
+            rc = sort_by_rank_z(h, h->cur, &res, true);
+            if (rc) return rc;
+            rc = enqueue_gen_reduce(h, res, 1 - res, 1 - mx_branch);
+            if (rc) return rc;
+            h->cur = 1 - res;
+            h->mx = 1 - mx_branch;
+            h->pend = eps;
+            Ctrl cg;
+            rc = read_ctrl(h, &cg);
+            if (rc) return rc;
+            if (cg.err) return fail(PS_ERR_DEVICE, "general gate: kernel error bits 0x%x", cg.err);
+            h->n_host = cg.nf[h->cur] + cg.nb[h->cur];
         }
         h->gates_applied = (si < stages.size()) ? stages[si].gate_first : n_gates;
         // grow ahead of a layer when the operator is close to the capacity

@@ -1,0 +1,251 @@
+// General Pauli rotations on gfx950: any generator sigma_J (several qubits,
+// X, Y and Z letters, any angle), for gates outside the streaming RX merge and
+// the fused Z-only Clifford pass.  Eq. update_rule: a string sigma_P that
+// commutes with sigma_J is unchanged; one that anticommutes keeps cos(theta)
+// times its coefficient and sends +-sin(theta) times it to the child
+// sigma_C = sigma_(P xor J).  Every key receives at most two contributions (its
+// own parent part and the child of its partner), so after the branch pass and
+// a full sort by (x, z) a merge of adjacent equal keys completes the gate.
+#include "orqa_device.h"
+
+namespace orqa {
+
+// Child sign: sigma_C sigma_J = i^e sigma_P with
+// e = |x_C & z_C| + |x_J & z_J| + 2 |z_C & x_J| - |x_P & z_P| (mod 4)
+// (sigma(x, z) = i^|x&z| X^x Z^z and Z^a X^b = (-1)^(a.b) X^b Z^a); the child's
+// coefficient is -sin(theta) c_P for e = 1 and +sin(theta) c_P for e = 3.  For
+// x_J = 0 this is the Z-only rule of the Clifford pass, for sigma_J = X_q the
+// rule of the RX merge.
+__device__ __forceinline__ bool gen_child_negative(const ulonglong2& xp, const ulonglong2& zp, const ulonglong2& xc,
+                                                   const ulonglong2& zc, const ulonglong2& xj, const ulonglong2& zj) {
+    const int e = k_popc_and(xc, zc) + k_popc_and(xj, zj) + 2 * k_popc_and(zc, xj) - k_popc_and(xp, zp);
+    return (e & 3) == 1;
+}
+
+template <typename CT, int LP>
+__device__ __forceinline__ bool gen_keep(const CT* c, const double* thr) {
+    bool keep = false;
+#pragma unroll
+    for (int a = 0; a < LP; ++a) keep |= absd(c[a]) > thr[a];
+    return keep;
+}
+
+// Branch: reads the (virtual, x-rotated) input, applies the pending truncation,
+// writes parents and children compacted to the front of the output in true
+// x.  Output offsets by a two-level decoupled look-back over tiles.
+template <typename CT, int LP>
+__global__ __launch_bounds__(kThreads) void k_gen_branch(GenArgs A, GateTrig g) {
+    __shared__ uint32_t sWave[4];
+    __shared__ uint32_t sTile;
+    __shared__ uint64_t sBase;
+    __shared__ double sThr[LP];
+    Ctrl* ctrl = A.ctrl;
+    const CT* __restrict__ Cin = static_cast<const CT*>(A.Cin);
+    CT* __restrict__ Cout = static_cast<CT*>(A.Cout);
+    const int tid = threadIdx.x, wave = tid >> 6;
+    const bool skip = ctrl->err != 0u;
+    const uint64_t nf = ctrl->nf[A.in_buf];
+    const uint64_t n = nf + ctrl->nb[A.in_buf];
+    const uint64_t ntiles = skip ? 0 : (n + kGenTile - 1) / kGenTile;
+    const uint32_t ep = ctrl->epoch;
+    const bool filt = A.eps_in > 0.0;
+    if (tid < LP) sThr[tid] = filt ? A.eps_in * bits_to_d(ctrl->maxbits[A.mx_in][tid]) : -1.0;
+    __syncthreads();
+    const ulonglong2 xj = make_ulonglong2(A.xj0, A.xj1), zj = make_ulonglong2(A.zj0, A.zj1);
+
+    for (;;) {
+        const uint32_t tile = acquire_tile(ctrl, &sTile);
+        if (tile >= ntiles) break;
+        const uint64_t t0 = uint64_t(tile) * kGenTile;
+        ulonglong2 xs[kGenIPT], zs[kGenIPT];
+        uint32_t nout[kGenIPT];
+        uint32_t cnt = 0;
+#pragma unroll
+        for (int k = 0; k < kGenIPT; ++k) {
+            const uint64_t i = t0 + uint64_t(k) * kThreads + tid;
+            nout[k] = 0;
+            xs[k] = make_ulonglong2(0, 0);
+            zs[k] = make_ulonglong2(0, 0);
+            if (i >= n) continue;
+            const uint64_t p = vphys(i, nf, A.cap);
+            xs[k] = rotl_n(A.Xin[p], A.xrot, A.nq);
+            zs[k] = A.Zin[p];
+            if (filt && !gen_keep<CT, LP>(Cin + p * LP, sThr)) continue;
+            const bool anti = ((k_popc_and(xs[k], zj) + k_popc_and(zs[k], xj)) & 1) != 0;
+            nout[k] = anti ? uint32_t(g.any_c != 0) + uint32_t(g.any_s != 0) : 1u;
+            cnt += nout[k];
+        }
+        uint32_t tot;
+        const uint32_t off = block_excl_scan(cnt, sWave, tot);
+        if (wave == 0) {
+            const uint64_t gmax = A.max_tiles / 64 + 2;
+            const uint64_t b = lookback_wave2(A.status, A.status + 2 * A.max_tiles, tile, ep, tot, &ctrl->err);
+            (void)gmax;
+            if (lane_id() == 0) sBase = b;
+        }
+        __syncthreads();
+        const uint64_t base = sBase;
+        if (tile == ntiles - 1 && tid == 0) {
+            const uint64_t total = base + tot;
+            if (total > A.cap) {
+                atomicOr(&ctrl->err, kErrCapacity);
+                atomicMax(reinterpret_cast<unsigned long long*>(&ctrl->need), static_cast<unsigned long long>(total));
+            } else {
+                ctrl->nf[A.out_buf] = total;
+                ctrl->nb[A.out_buf] = 0;
+            }
+        }
+        uint64_t o = base + off;
+#pragma unroll
+        for (int k = 0; k < kGenIPT; ++k) {
+            if (nout[k] == 0) continue;
+            const uint64_t i = t0 + uint64_t(k) * kThreads + tid;
+            const CT* ce = Cin + vphys(i, nf, A.cap) * LP;
+            const bool anti = ((k_popc_and(xs[k], zj) + k_popc_and(zs[k], xj)) & 1) != 0;
+            if (!anti) {  // commutes: unchanged
+                if (o < A.cap) {
+                    A.Xout[o] = xs[k];
+                    A.Zout[o] = zs[k];
+#pragma unroll
+                    for (int a = 0; a < LP; ++a) Cout[o * LP + a] = ce[a];
+                }
+                ++o;
+                continue;
+            }
+            if (g.any_c) {
+                if (o < A.cap) {
+                    A.Xout[o] = xs[k];
+                    A.Zout[o] = zs[k];
+#pragma unroll
+                    for (int a = 0; a < LP; ++a) Cout[o * LP + a] = Arith<CT>::scale_c(g, a, ce[a]);
+                }
+                ++o;
+            }
+            if (g.any_s) {
+                const ulonglong2 xc = make_ulonglong2(xs[k].x ^ xj.x, xs[k].y ^ xj.y);
+                const ulonglong2 zc = make_ulonglong2(zs[k].x ^ zj.x, zs[k].y ^ zj.y);
+                const bool neg = gen_child_negative(xs[k], zs[k], xc, zc, xj, zj);
+                if (o < A.cap) {
+                    A.Xout[o] = xc;
+                    A.Zout[o] = zc;
+#pragma unroll
+                    for (int a = 0; a < LP; ++a) Cout[o * LP + a] = Arith<CT>::scale_s(g, a, ce[a], neg);
+                }
+                ++o;
+            }
+        }
+        __syncthreads();
+    }
+    if (finish_launch(ctrl)) {
+        if (__hip_atomic_load(&ctrl->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u) {
+            for (int a = 0; a < kMaxLanes; ++a) ctrl->maxbits[A.mx_in][a] = 0ull;
+            if (ntiles == 0) {
+                ctrl->nf[A.out_buf] = 0;
+                ctrl->nb[A.out_buf] = 0;
+            }
+            ctrl->stages_done += 1;
+            ctrl->cnt_updates += n;
+        }
+    }
+}
+
+// Merge: the input is sorted by (x, z) (front run only); each key appears at
+// most twice (a parent part and a child part) and its entries are summed.
+// Writes the unique keys compacted and the per-lane max of the results.
+template <typename CT, int LP>
+__global__ __launch_bounds__(kThreads) void k_gen_reduce(GenArgs A) {
+    __shared__ uint32_t sWave[4];
+    __shared__ uint32_t sTile;
+    __shared__ uint64_t sBase;
+    Ctrl* ctrl = A.ctrl;
+    const CT* __restrict__ Cin = static_cast<const CT*>(A.Cin);
+    CT* __restrict__ Cout = static_cast<CT*>(A.Cout);
+    const int tid = threadIdx.x, wave = tid >> 6;
+    const bool skip = ctrl->err != 0u;
+    const uint64_t n = ctrl->nf[A.in_buf];
+    const uint64_t ntiles = skip ? 0 : (n + kGenTile - 1) / kGenTile;
+    const uint32_t ep = ctrl->epoch;
+    double vmax[LP];
+#pragma unroll
+    for (int a = 0; a < LP; ++a) vmax[a] = 0.0;
+
+    for (;;) {
+        const uint32_t tile = acquire_tile(ctrl, &sTile);
+        if (tile >= ntiles) break;
+        const uint64_t t0 = uint64_t(tile) * kGenTile;
+        // thread owns consecutive positions (blocked), so the scan keeps key order
+        const uint64_t i0 = t0 + uint64_t(tid) * kGenIPT;
+        uint32_t first = 0, cnt = 0;
+#pragma unroll
+        for (int k = 0; k < kGenIPT; ++k) {
+            const uint64_t i = i0 + k;
+            if (i >= n) continue;
+            const ulonglong2 x = A.Xin[i], z = A.Zin[i];
+            const bool f = i == 0 || !k_eq(x, A.Xin[i - 1]) || !k_eq(z, A.Zin[i - 1]);
+            if (f && i + 2 < n && k_eq(x, A.Xin[i + 2]) && k_eq(z, A.Zin[i + 2]))
+                atomicOr(&ctrl->err, kErrInternal);  // three entries of one key cannot occur
+            first |= uint32_t(f) << k;
+            cnt += f;
+        }
+        uint32_t tot;
+        const uint32_t off = block_excl_scan(cnt, sWave, tot);
+        if (wave == 0) {
+            const uint64_t b = lookback_wave2(A.status, A.status + 2 * A.max_tiles, tile, ep, tot, &ctrl->err);
+            if (lane_id() == 0) sBase = b;
+        }
+        __syncthreads();
+        const uint64_t base = sBase;
+        if (tile == ntiles - 1 && tid == 0) {
+            ctrl->nf[A.out_buf] = base + tot;
+            ctrl->nb[A.out_buf] = 0;
+        }
+        uint64_t o = base + off;
+#pragma unroll
+        for (int k = 0; k < kGenIPT; ++k) {
+            if (!((first >> k) & 1u)) continue;
+            const uint64_t i = i0 + k;
+            const ulonglong2 x = A.Xin[i], z = A.Zin[i];
+            const bool two = i + 1 < n && k_eq(x, A.Xin[i + 1]) && k_eq(z, A.Zin[i + 1]);
+            A.Xout[o] = x;
+            A.Zout[o] = z;
+#pragma unroll
+            for (int a = 0; a < LP; ++a) {
+                CT v = Cin[i * LP + a];
+                if (two) v = v + Cin[(i + 1) * LP + a];
+                Cout[o * LP + a] = v;
+                vmax[a] = fmax(vmax[a], absd(v));
+            }
+            ++o;
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int a = 0; a < LP; ++a) {
+        const double mx = wave_max_d(vmax[a]);
+        if (lane_id() == 0 && mx > 0.0)
+            atomicMax(reinterpret_cast<unsigned long long*>(&ctrl->maxbits[A.mx_out][a]),
+                      static_cast<unsigned long long>(d_to_bits(mx)));
+    }
+    if (finish_launch(ctrl)) {
+        if (ntiles == 0 && __hip_atomic_load(&ctrl->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u) {
+            ctrl->nf[A.out_buf] = 0;
+            ctrl->nb[A.out_buf] = 0;
+        }
+    }
+}
+
+hipError_t launch_gen_branch(const GenArgs& a, const GateTrig& g, int dtype, int lp, hipStream_t s, int grid) {
+#define L_GB(T, L) k_gen_branch<T, L><<<dim3(grid), dim3(kThreads), 0, s>>>(a, g)
+    ORQA_DISPATCH(dtype, lp, L_GB);
+#undef L_GB
+    return hipGetLastError();
+}
+
+hipError_t launch_gen_reduce(const GenArgs& a, int dtype, int lp, hipStream_t s, int grid) {
+#define L_GR(T, L) k_gen_reduce<T, L><<<dim3(grid), dim3(kThreads), 0, s>>>(a)
+    ORQA_DISPATCH(dtype, lp, L_GR);
+#undef L_GR
+    return hipGetLastError();
+}
+
+}  // namespace orqa

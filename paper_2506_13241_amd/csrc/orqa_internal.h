@@ -26,7 +26,7 @@ constexpr int kCompactIPT = 4;
 constexpr int kCompactTile = kThreads * kCompactIPT;  // 1024
 constexpr int kSortIPT = 8;
 constexpr int kSortTile = kThreads * kSortIPT;  // 2048
-constexpr int kSortDigits = 20;                 // 16 byte digits of z, 4 of the group rank
+constexpr int kSortDigits = 36;                 // 16 byte digits of z, 4 of the group rank, 16 of x
 constexpr int kReduceBlocks = 512;
 
 // Device-resident control block of a handle.  The two state buffers each hold
@@ -146,8 +146,8 @@ struct SortPassArgs {
 hipError_t launch_rx_partition(const RxArgs& a, hipStream_t s);
 hipError_t launch_rx(const RxArgs& a, const GateTrig& g, int dtype, int lp, hipStream_t s, int grid);
 hipError_t launch_compact(const CompactArgs& a, int dtype, int lp, hipStream_t s, int grid);
-hipError_t launch_sort_hist(Ctrl* ctrl, int buf, const uint32_t* R, const ulonglong2* Z, uint32_t* hist,
-                            hipStream_t s, int grid);
+hipError_t launch_sort_hist(Ctrl* ctrl, int buf, const uint32_t* R, const ulonglong2* Z, const ulonglong2* X,
+                            int with_x, uint32_t* hist, hipStream_t s, int grid);
 hipError_t launch_sort_pass(const SortPassArgs& a, int dtype, int lp, hipStream_t s, int grid);
 
 // Re-sort after a Clifford layer when every x-group is small: each group is
@@ -168,6 +168,56 @@ struct GroupSortArgs {
     void* Cd;
 };
 hipError_t launch_group_sort(const GroupSortArgs& a, int dtype, int lp, hipStream_t s, int grid);
+
+// General Pauli rotation (any sigma_J): branch every string into its parent
+// part and, when it anticommutes with sigma_J, its child I xor J (unsorted,
+// true x); after a full (x, z) sort, merge the at most two entries per key.
+constexpr int kGenIPT = 4;
+constexpr int kGenTile = kThreads * kGenIPT;
+struct GenArgs {
+    Ctrl* ctrl;
+    int in_buf, out_buf, mx_in, mx_out;
+    const ulonglong2* Xin;
+    const ulonglong2* Zin;
+    const void* Cin;
+    ulonglong2* Xout;
+    ulonglong2* Zout;
+    void* Cout;
+    uint64_t cap;
+    uint64_t* status;
+    uint64_t max_tiles;
+    double eps_in;  // pending truncation threshold of the input (<= 0: none)
+    int xrot, nq;
+    uint64_t xj0, xj1, zj0, zj1;  // the generator sigma_J
+};
+hipError_t launch_gen_branch(const GenArgs& a, const GateTrig& g, int dtype, int lp, hipStream_t s, int grid);
+hipError_t launch_gen_reduce(const GenArgs& a, int dtype, int lp, hipStream_t s, int grid);
+
+#define ORQA_DISPATCH(DTYPE, LP, F)                      \
+    do {                                                 \
+        if ((DTYPE) == 0) {                              \
+            switch (LP) {                                \
+                case 1: F(double, 1); break;             \
+                case 2: F(double, 2); break;             \
+                case 4: F(double, 4); break;             \
+                case 8: F(double, 8); break;             \
+                case 16: F(double, 16); break;           \
+                case 32: F(double, 32); break;           \
+                default: return hipErrorInvalidValue;    \
+            }                                            \
+        } else {                                         \
+            switch (LP) {                                \
+                case 1: F(float, 1); break;              \
+                case 2: F(float, 2); break;              \
+                case 4: F(float, 4); break;              \
+                case 8: F(float, 8); break;              \
+                case 16: F(float, 16); break;            \
+                case 32: F(float, 32); break;            \
+                default: return hipErrorInvalidValue;    \
+            }                                            \
+        }                                                \
+    } while (0)
+
 hipError_t launch_reduce(Ctrl* ctrl, int buf, const ulonglong2* X, const void* C, uint64_t cap, int mode,
                          double* partial, double* out, int dtype, int lp, int lanes, hipStream_t s);
 hipError_t launch_fill_u64(uint64_t* p, uint64_t v, size_t n, hipStream_t s);

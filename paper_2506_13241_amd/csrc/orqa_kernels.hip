@@ -626,15 +626,20 @@ __global__ __launch_bounds__(kThreads) void k_compact(CompactArgs A) {
 // one stable pass per digit with decoupled look-back across tiles for the
 // 256 bucket offsets (Adinets & Merrill, "Onesweep", 2022).
 
-__device__ __forceinline__ uint32_t sort_digit(int digit, uint32_t r, const ulonglong2& z) {
+// Digits of the radix sort, least significant first: 0..15 bytes of z (low
+// word first), 16..19 bytes of the x-group rank, 20..35 bytes of x.
+__device__ __forceinline__ uint32_t sort_digit(int digit, uint32_t r, const ulonglong2& z, const ulonglong2& x) {
     if (digit < 8) return uint32_t(z.x >> (8 * digit)) & 0xFFu;
     if (digit < 16) return uint32_t(z.y >> (8 * (digit - 8))) & 0xFFu;
-    return (r >> (8 * (digit - 16))) & 0xFFu;
+    if (digit < 20) return (r >> (8 * (digit - 16))) & 0xFFu;
+    if (digit < 28) return uint32_t(x.x >> (8 * (digit - 20))) & 0xFFu;
+    return uint32_t(x.y >> (8 * (digit - 28))) & 0xFFu;
 }
 
 __global__ __launch_bounds__(kThreads) void k_sort_hist(const Ctrl* __restrict__ ctrl, int buf,
                                                         const uint32_t* __restrict__ R,
                                                         const ulonglong2* __restrict__ Z,
+                                                        const ulonglong2* __restrict__ X, int with_x,
                                                         uint32_t* __restrict__ hist) {
     __shared__ uint32_t sh[kSortDigits][256];
     for (int i = threadIdx.x; i < kSortDigits * 256; i += kThreads) (&sh[0][0])[i] = 0;
@@ -643,9 +648,17 @@ __global__ __launch_bounds__(kThreads) void k_sort_hist(const Ctrl* __restrict__
     if (!ctrl->err) {
         for (uint64_t i = blockIdx.x * uint64_t(kThreads) + threadIdx.x; i < n; i += uint64_t(gridDim.x) * kThreads) {
             const ulonglong2 z = Z[i];
-            const uint32_t r = R[i];
+            if (with_x) {  // full key (x, z): z and x digits, no rank
+                const ulonglong2 x = X[i];
 #pragma unroll
-            for (int d = 0; d < kSortDigits; ++d) atomicAdd(&sh[d][sort_digit(d, r, z)], 1u);
+                for (int d = 0; d < 16; ++d) atomicAdd(&sh[d][sort_digit(d, 0, z, x)], 1u);
+#pragma unroll
+                for (int d = 20; d < kSortDigits; ++d) atomicAdd(&sh[d][sort_digit(d, 0, z, x)], 1u);
+            } else {  // (x-group rank, z)
+                const uint32_t r = R[i];
+#pragma unroll
+                for (int d = 0; d < 20; ++d) atomicAdd(&sh[d][sort_digit(d, r, z, z)], 1u);
+            }
         }
     }
     __syncthreads();
@@ -683,7 +696,8 @@ __global__ __launch_bounds__(kThreads) void k_sort_pass(SortPassArgs A) {
             const uint64_t i = seg + uint64_t(k) * 64 + lane;
             const bool valid = i < A.n;
             uint32_t d = 0;
-            if (valid) d = sort_digit(A.digit, A.Rs[i], A.Zs[i]);
+            if (valid) d = A.digit < 20 ? sort_digit(A.digit, A.Rs[i], A.Zs[i], A.Zs[i])
+                                         : sort_digit(A.digit, 0, A.Zs[i], A.Xs[i]);
             dig[k] = valid ? d : 0xFFFFFFFFu;
             uint64_t peers = __ballot(valid);
 #pragma unroll
@@ -803,31 +817,6 @@ __global__ void k_fill_u64(uint64_t* p, uint64_t v, size_t n) {
 
 // ================================================================ launchers
 
-#define ORQA_DISPATCH(DTYPE, LP, F)                      \
-    do {                                                 \
-        if ((DTYPE) == 0) {                              \
-            switch (LP) {                                \
-                case 1: F(double, 1); break;             \
-                case 2: F(double, 2); break;             \
-                case 4: F(double, 4); break;             \
-                case 8: F(double, 8); break;             \
-                case 16: F(double, 16); break;           \
-                case 32: F(double, 32); break;           \
-                default: return hipErrorInvalidValue;    \
-            }                                            \
-        } else {                                         \
-            switch (LP) {                                \
-                case 1: F(float, 1); break;              \
-                case 2: F(float, 2); break;              \
-                case 4: F(float, 4); break;              \
-                case 8: F(float, 8); break;              \
-                case 16: F(float, 16); break;            \
-                case 32: F(float, 32); break;            \
-                default: return hipErrorInvalidValue;    \
-            }                                            \
-        }                                                \
-    } while (0)
-
 hipError_t launch_rx_partition(const RxArgs& a, hipStream_t s) {
     k_rx_partition<<<dim3(256), dim3(kThreads), 0, s>>>(a.ctrl, a.in_buf, a.Xin, a.Zin, a.cap, a.desc);
     return hipGetLastError();
@@ -847,9 +836,9 @@ hipError_t launch_compact(const CompactArgs& a, int dtype, int lp, hipStream_t s
     return hipGetLastError();
 }
 
-hipError_t launch_sort_hist(Ctrl* ctrl, int buf, const uint32_t* R, const ulonglong2* Z, uint32_t* hist,
-                            hipStream_t s, int grid) {
-    k_sort_hist<<<dim3(grid), dim3(kThreads), 0, s>>>(ctrl, buf, R, Z, hist);
+hipError_t launch_sort_hist(Ctrl* ctrl, int buf, const uint32_t* R, const ulonglong2* Z, const ulonglong2* X,
+                            int with_x, uint32_t* hist, hipStream_t s, int grid) {
+    k_sort_hist<<<dim3(grid), dim3(kThreads), 0, s>>>(ctrl, buf, R, Z, X, with_x, hist);
     return hipGetLastError();
 }
 

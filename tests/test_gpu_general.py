@@ -1,0 +1,139 @@
+"""General Pauli rotations on the HIP path (needs a GPU): any generator
+sigma_J, any angle, in any order, against the oracle (whose update rule and
+signs are pinned by the dense brute force).  Binary64 runs must be
+bit-identical: every key receives at most a parent part and a child part, and
+both sides form the same two rounded products and one sum."""
+
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import workload as w
+from oracle import OracleSum
+from oracle.statevector import kicked_ising_magnetization
+from gpu_common import assert_same_operator, gpu_sum
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def _both(n, terms, coeffs, dtype=0):
+    return gpu_sum(n, terms, coeffs, dtype=dtype), OracleSum(n, terms, coeffs)
+
+
+@pytest.mark.parametrize("eps0", [0.0, 1e-3])
+def test_random_rotations_small_register(eps0):
+    """40 random rotations (weights 1-4, X/Y/Z letters, 20% at Clifford
+    angles) on a random 8-qubit set."""
+    n = 8
+    terms, coeffs = w.random_pauli_set(n, 300, seed=41)
+    gates = w.random_gates(n, 40, seed=42, max_weight=4)
+    g, o = _both(n, terms, coeffs)
+    for k in range(0, 40, 8):  # several layers, so state carries across calls
+        sub = w.GateList(gates.gens[k:k + 8], gates.thetas[k:k + 8])
+        g.apply_rotation_layer(sub, eps0)
+        o.apply(sub, eps0)
+        assert_same_operator(g, o, coeff_exact=True)
+    say(f"small register eps0={eps0}: |O| = {g.size()}")
+
+
+def test_random_rotations_127_qubits_many_tiles():
+    """Rotations of weight <= 3 on the 127-q register on ~50k strings
+    (many tiles of the branch and merge passes), eps0 = 1e-4."""
+    n = 127
+    lat = w.eagle_127()
+    terms, coeffs = w.random_pauli_set(n, 50000, seed=43, support=w.ball(lat, 62, 4))
+    sup = w.ball(lat, 62, 3)
+    gates = w.random_gates(len(sup), 12, seed=44, max_weight=3)
+    # map the generators from the compact register onto the ball's qubits
+    gens = []
+    for row in gates.gens:
+        ops = {}
+        for j, q in enumerate(sup):
+            xb = (int(row[j >> 6]) >> (j & 63)) & 1
+            zb = (int(row[2 + (j >> 6)]) >> (j & 63)) & 1
+            if xb or zb:
+                ops[q] = "X" if (xb and not zb) else ("Y" if xb else "Z")
+        gens.append(w.pauli_words(n, ops))
+    gl = w.GateList(np.stack(gens), gates.thetas)
+    g, o = _both(n, terms, coeffs)
+    g.apply_rotation_layer(gl, 1e-4)
+    o.apply(gl, 1e-4)
+    say(f"127q random rotations: |O| = {g.size()}")
+    assert_same_operator(g, o, coeff_exact=True)
+
+
+def test_rx_out_of_order_and_general_gate_inside_an_rx_run():
+    """RX on qubits 0, 1, 2 (streaming path), then RY on qubit 7 while the
+    stored x is rotated, then RX on 0 again and RX in descending order."""
+    n = 12
+    terms, coeffs = w.random_pauli_set(n, 2000, seed=45)
+    def rot(ops, th):
+        return w.pauli_words(n, ops), th
+    seq = [rot({0: "X"}, 0.3), rot({1: "X"}, 0.4), rot({2: "X"}, 0.5), rot({7: "Y"}, 0.6),
+           rot({0: "X"}, 0.7), rot({5: "X"}, 0.2), rot({4: "X"}, 0.1), rot({3: "Z", 9: "Z"}, 0.9)]
+    gl = w.GateList(np.stack([s[0] for s in seq]), np.array([[s[1]] for s in seq]))
+    g, o = _both(n, terms, coeffs)
+    g.apply_rotation_layer(gl, 1e-5)
+    o.apply(gl, 1e-5)
+    assert_same_operator(g, o, coeff_exact=True)
+    # the streaming path resumes at qubit 0 after a general gate
+    rx = w.GateList(np.stack([w.pauli_words(n, {q: "X"}) for q in range(n)]), np.full((n, 1), 0.35))
+    g.apply_rotation_layer(rx, 1e-5)
+    o.apply(rx, 1e-5)
+    assert_same_operator(g, o, coeff_exact=True)
+
+
+def test_non_clifford_zz_kicked_ising_patch():
+    """Kicked Ising on the 21-q patch with theta_zz = -1.0 (not Clifford, so
+    every RZZ takes the general path): equal to the oracle for 3 steps and to
+    the statevector for 4."""
+    lat = w.heavy_hex_21()
+    zz, rx = w.kicked_ising_step(lat, 0.6, theta_zz=-1.0)
+    terms, coef = w.single_pauli_term(lat.n, {10: "Z"})
+    g, o = _both(lat.n, terms, coef)
+    exact = kicked_ising_magnetization(lat.n, lat.edges, 10, 0.6, 4, theta_zz=-1.0)
+    for t in range(4):
+        g.apply_rotation_layer(zz).apply_rotation_layer(rx)
+        if t < 3:
+            o.apply(zz).apply(rx)
+            assert_same_operator(g, o, coeff_exact=True)
+        say(f"theta_zz=-1 step {t + 1}: |O| = {g.size()} <Z> = {g.expectation_z()[0]:.12f} exact {exact[t]:.12f}")
+        assert abs(g.expectation_z()[0] - exact[t]) <= 1e-11
+
+
+def test_general_gates_with_lanes_and_binary32():
+    n = 9
+    terms, coeffs = w.random_pauli_set(n, 500, seed=47, lanes=3)
+    gates = w.random_gates(n, 10, seed=48, max_weight=3, lanes=3)
+    g, o = _both(n, terms, coeffs)
+    g.apply_rotation_layer(gates, 1e-4)
+    o.apply(gates, 1e-4)
+    assert_same_operator(g, o, coeff_exact=True)
+    g32 = gpu_sum(n, terms, coeffs, dtype=1)
+    g64 = gpu_sum(n, terms, coeffs, dtype=0)
+    g32.apply_rotation_layer(gates)
+    g64.apply_rotation_layer(gates)
+    k32, c32 = g32.export()
+    k64, c64 = g64.export()
+    assert np.array_equal(k32, k64)
+    assert np.abs(c32.astype(np.float64) - c64).max() <= 1e-5 * np.abs(c64).max()
+
+
+def test_general_gate_capacity_growth():
+    """A weight-6 rotation doubles ~40k anticommuting strings from a small
+    capacity: the branch runs out of room, the handle grows and re-runs it."""
+    n = 16
+    terms, coeffs = w.random_pauli_set(n, 40000, seed=49)
+    gate = w.GateList(w.pauli_words(n, {0: "Y", 3: "X", 5: "Z", 8: "Y", 11: "X", 14: "Z"})[None, :],
+                      np.array([[0.77]]))
+    g = gpu_sum(n, terms, coeffs, capacity=45000)
+    o = OracleSum(n, terms, coeffs)
+    g.apply_rotation_layer(gate)
+    o.apply(gate)
+    assert_same_operator(g, o, coeff_exact=True)
