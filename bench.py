@@ -65,7 +65,7 @@ def measured_traffic():
     return None, None
 
 
-def cpu_baseline(theta, eps0, budget_s):
+def cpu_baseline(theta, eps0, budget_s, theta_zz=-math.pi / 2):
     """The FP64 std::map oracle, single-threaded, on a bounded sample of the
     same workload: Trotter steps 1.. from the start, gate by gate, until the
     time budget is spent.  Same metric (string-updates/s)."""
@@ -77,7 +77,7 @@ def cpu_baseline(theta, eps0, budget_s):
     lat = w.eagle_127()
     terms, coef = w.single_pauli_term(lat.n, {62: "Z"})
     o = OracleSum(lat.n, terms, coef)
-    zz, rx = w.kicked_ising_step(lat, theta)
+    zz, rx = w.kicked_ising_step(lat, theta, theta_zz=theta_zz)
     gates = w.GateList.concat([zz, rx])
     t0 = time.perf_counter()
     n_gates = 0
@@ -110,6 +110,8 @@ def main():
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=18)
     ap.add_argument("--theta", type=float, default=0.8)
+    ap.add_argument("--theta-zz", type=float, default=-math.pi / 2,
+                    help="RZZ angle; away from multiples of pi/2 every RZZ takes the general-rotation path")
     ap.add_argument("--eps", type=float, default=1e-4)
     ap.add_argument("--dtype", choices=["f64", "f32"], default="f64")
     ap.add_argument("--reference-f64", action="store_true",
@@ -152,7 +154,7 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     lat = w.eagle_127()
-    zz, rx = w.kicked_ising_step(lat, args.theta)
+    zz, rx = w.kicked_ising_step(lat, args.theta, theta_zz=args.theta_zz)
     terms, coef = w.single_pauli_term(lat.n, {62: "Z"})
     dtype = P.PS_F64 if args.dtype == "f64" else P.PS_F32
     ps = P.PauliSum(lat.n, terms, coef, dtype=dtype, capacity=1 << 22)
@@ -242,7 +244,7 @@ def main():
         extra["dz_vs_f64_max"] = max(d)
     cpu = None
     if not args.no_cpu_baseline and args.trunc == "magnitude":
-        cpu, ez_cpu = cpu_baseline(args.theta, args.eps, args.cpu_budget)
+        cpu, ez_cpu = cpu_baseline(args.theta, args.eps, args.cpu_budget, args.theta_zz)
         k = min(len(ez_cpu), len(ez_all))
         if k:
             extra["dz_vs_oracle_max"] = max(abs(a - b) for a, b in zip(ez_all[:k], ez_cpu[:k]))
@@ -261,8 +263,9 @@ def main():
         "dtype": args.dtype,
         "data": "synthetic: deterministic kicked-Ising circuit, no dataset",
         "config": {
-            "workload": f"kicked Ising 127q heavy-hex, O0=Z62, theta_h={args.theta}, theta_zz=-pi/2, "
-                        f"eps0={args.eps} per gate"
+            "workload": f"kicked Ising 127q heavy-hex, O0=Z62, theta_h={args.theta}, "
+                        + ("theta_zz=-pi/2, " if abs(args.theta_zz + math.pi / 2) < 1e-15 else f"theta_zz={args.theta_zz}, ")
+                        + f"eps0={args.eps} per gate"
                         + (" + learned truncation once per step" if args.trunc == "learned" else "")
                         + f", Trotter steps {args.warmup + 1}-{args.warmup + args.steps}",
             "qubits": 127,

@@ -542,6 +542,7 @@ int enqueue_gen_branch(ps_handle* h, int in, int out, int mx_in, double eps_in, 
     a.xj1 = st.gen.x[1];
     a.zj0 = st.gen.z[0];
     a.zj1 = st.gen.z[1];
+    a.keep_rot = (st.gen.x[0] | st.gen.x[1]) == 0 ? 1 : 0;
     size_t slot;
     int rc = ev_begin(h, 1, &slot);
     if (rc) return rc;
@@ -624,7 +625,7 @@ int run_rx_graph(ps_handle* h, const std::vector<GateTrig>& trigs, double pend0,
 
 // Re-sort buffer `b` (front only, with group ranks) by (rank, z).  Returns the
 // buffer holding the result in *result.
-int sort_by_rank_z(ps_handle* h, int b, int* result, bool full_key = false) {
+int sort_by_rank_z(ps_handle* h, int b, int* result, bool full_key = false, bool try_groups = true) {
     Ctrl c;
     int rc = read_ctrl(h, &c);
     if (rc) return rc;
@@ -632,7 +633,7 @@ int sort_by_rank_z(ps_handle* h, int b, int* result, bool full_key = false) {
     const uint64_t n = c.nf[b];
     *result = b;
     if (n <= 1) return PS_OK;
-    if (!full_key) {  // every x-group small enough: one pass sorts each group inside a workgroup
+    if (try_groups) {  // every x-group small enough: one pass sorts each group inside a workgroup
         GroupSortArgs g{};
         g.ctrl = h->ctrl;
         g.in_buf = b;
@@ -1038,7 +1039,7 @@ int apply_rotation_layer(ps_handle* h, const ps_pauli* gens, const double* theta
             t.any_c = any_c;
             t.any_s = any_s;
             stages.push_back(s);
-            xrot = 0;  // the general stage leaves x unrotated
+            if ((G.x[0] | G.x[1]) != 0) xrot = 0;  // x_J = 0 keeps the stored rotation, else x is unrotated
             ++g;
         }
     }
@@ -1063,7 +1064,7 @@ int apply_rotation_layer(ps_handle* h, const ps_pauli* gens, const double* theta
     size_t si = 0;
     while (si < stages.size()) {
         std::vector<Launched> launched;
-        bool sort_after = false, gen_after = false;
+        bool sort_after = false, gen_after = false, gen_zonly = false;
         for (; si < stages.size(); ++si) {
             Stage& s = stages[si];
             const bool noop = s.kind == ST_CLIFF && s.gens.empty() && !(h->pend > 0.0) && !(eps_learned > 0.0);
@@ -1095,7 +1096,8 @@ int apply_rotation_layer(ps_handle* h, const ps_pauli* gens, const double* theta
                 rc = enqueue_gen_branch(h, in, out, mx_in, h->pend, s);
                 if (rc) return rc;
                 h->cur = out;
-                h->xrot = 0;
+                gen_zonly = (s.gen.x[0] | s.gen.x[1]) == 0;
+                if (!gen_zonly) h->xrot = 0;
                 h->pend = -1.0;
                 gen_after = true;
                 ++si;
@@ -1164,7 +1166,9 @@ int apply_rotation_layer(ps_handle* h, const ps_pauli* gens, const double* theta
         if (gen_after) {  // general gate: sort the branch output by (x, z), merge equal keys
             const int mx_branch = h->mx;  // zeroed by the branch; the merge's max goes to the other slot
             int res = h->cur;
-            rc = sort_by_rank_z(h, h->cur, &res, true);
+            // x_J = 0: outputs stay in their x-groups, which keep their order:
+            // sort inside the groups; otherwise the full (x, z) radix sort
+            rc = sort_by_rank_z(h, h->cur, &res, true, gen_zonly);
             if (rc) return rc;
             rc = enqueue_gen_reduce(h, res, 1 - res, 1 - mx_branch);
             if (rc) return rc;

@@ -31,8 +31,10 @@ __device__ __forceinline__ bool gen_keep(const CT* c, const double* thr) {
 }
 
 // Branch: reads the (virtual, x-rotated) input, applies the pending truncation,
-// writes parents and children compacted to the front of the output in true
-// x.  Output offsets by a two-level decoupled look-back over tiles.
+// writes parents and children compacted to the front of the output, in input
+// order, in true x (or, when x_J = 0, with x as stored: then every output
+// stays in its parent's x-group and the groups keep their order).  Output
+// offsets by a two-level decoupled look-back over tiles.
 template <typename CT, int LP>
 __global__ __launch_bounds__(kThreads) void k_gen_branch(GenArgs A, GateTrig g) {
     __shared__ uint32_t sWave[4];
@@ -62,16 +64,17 @@ __global__ __launch_bounds__(kThreads) void k_gen_branch(GenArgs A, GateTrig g) 
         uint32_t cnt = 0;
 #pragma unroll
         for (int k = 0; k < kGenIPT; ++k) {
-            const uint64_t i = t0 + uint64_t(k) * kThreads + tid;
+            const uint64_t i = t0 + uint64_t(tid) * kGenIPT + k;  // blocked: outputs keep the input order
             nout[k] = 0;
             xs[k] = make_ulonglong2(0, 0);
             zs[k] = make_ulonglong2(0, 0);
             if (i >= n) continue;
             const uint64_t p = vphys(i, nf, A.cap);
-            xs[k] = rotl_n(A.Xin[p], A.xrot, A.nq);
+            xs[k] = A.Xin[p];  // as stored; the true x for the algebra below
             zs[k] = A.Zin[p];
             if (filt && !gen_keep<CT, LP>(Cin + p * LP, sThr)) continue;
-            const bool anti = ((k_popc_and(xs[k], zj) + k_popc_and(zs[k], xj)) & 1) != 0;
+            const ulonglong2 xt = rotl_n(xs[k], A.xrot, A.nq);
+            const bool anti = ((k_popc_and(xt, zj) + k_popc_and(zs[k], xj)) & 1) != 0;
             nout[k] = anti ? uint32_t(g.any_c != 0) + uint32_t(g.any_s != 0) : 1u;
             cnt += nout[k];
         }
@@ -99,12 +102,14 @@ __global__ __launch_bounds__(kThreads) void k_gen_branch(GenArgs A, GateTrig g) 
 #pragma unroll
         for (int k = 0; k < kGenIPT; ++k) {
             if (nout[k] == 0) continue;
-            const uint64_t i = t0 + uint64_t(k) * kThreads + tid;
+            const uint64_t i = t0 + uint64_t(tid) * kGenIPT + k;
             const CT* ce = Cin + vphys(i, nf, A.cap) * LP;
-            const bool anti = ((k_popc_and(xs[k], zj) + k_popc_and(zs[k], xj)) & 1) != 0;
+            const ulonglong2 xt = rotl_n(xs[k], A.xrot, A.nq);
+            const ulonglong2 xw = A.keep_rot ? xs[k] : xt;  // x as written
+            const bool anti = ((k_popc_and(xt, zj) + k_popc_and(zs[k], xj)) & 1) != 0;
             if (!anti) {  // commutes: unchanged
                 if (o < A.cap) {
-                    A.Xout[o] = xs[k];
+                    A.Xout[o] = xw;
                     A.Zout[o] = zs[k];
 #pragma unroll
                     for (int a = 0; a < LP; ++a) Cout[o * LP + a] = ce[a];
@@ -114,7 +119,7 @@ __global__ __launch_bounds__(kThreads) void k_gen_branch(GenArgs A, GateTrig g) 
             }
             if (g.any_c) {
                 if (o < A.cap) {
-                    A.Xout[o] = xs[k];
+                    A.Xout[o] = xw;
                     A.Zout[o] = zs[k];
 #pragma unroll
                     for (int a = 0; a < LP; ++a) Cout[o * LP + a] = Arith<CT>::scale_c(g, a, ce[a]);
@@ -122,11 +127,11 @@ __global__ __launch_bounds__(kThreads) void k_gen_branch(GenArgs A, GateTrig g) 
                 ++o;
             }
             if (g.any_s) {
-                const ulonglong2 xc = make_ulonglong2(xs[k].x ^ xj.x, xs[k].y ^ xj.y);
+                const ulonglong2 xc = make_ulonglong2(xt.x ^ xj.x, xt.y ^ xj.y);
                 const ulonglong2 zc = make_ulonglong2(zs[k].x ^ zj.x, zs[k].y ^ zj.y);
-                const bool neg = gen_child_negative(xs[k], zs[k], xc, zc, xj, zj);
+                const bool neg = gen_child_negative(xt, zs[k], xc, zc, xj, zj);
                 if (o < A.cap) {
-                    A.Xout[o] = xc;
+                    A.Xout[o] = A.keep_rot ? xw : xc;  // keep_rot only for x_J = 0: same x
                     A.Zout[o] = zc;
 #pragma unroll
                     for (int a = 0; a < LP; ++a) Cout[o * LP + a] = Arith<CT>::scale_s(g, a, ce[a], neg);

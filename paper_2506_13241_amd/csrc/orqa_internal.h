@@ -154,7 +154,7 @@ hipError_t launch_sort_pass(const SortPassArgs& a, int dtype, int lp, hipStream_
 // sorted by z inside one workgroup, in place of the groups' positions.
 constexpr int kGsThreads = 512;
 constexpr int kGsTile = 1024;                  // positions whose groups a workgroup sorts
-constexpr int kGsMaxGroup = 2048;              // larger groups: radix-sort fallback
+constexpr int kGsMaxGroup = 3072;              // larger groups: radix-sort fallback
 constexpr int kGsCap = kGsTile + kGsMaxGroup;  // strings staged per tile
 constexpr int kGsIPT = kGsCap / kGsThreads;
 struct GroupSortArgs {
@@ -189,6 +189,7 @@ struct GenArgs {
     double eps_in;  // pending truncation threshold of the input (<= 0: none)
     int xrot, nq;
     uint64_t xj0, xj1, zj0, zj1;  // the generator sigma_J
+    int keep_rot;                  // x_J = 0: write x as stored (rotated), keep the x-group order
 };
 hipError_t launch_gen_branch(const GenArgs& a, const GateTrig& g, int dtype, int lp, hipStream_t s, int grid);
 hipError_t launch_gen_reduce(const GenArgs& a, int dtype, int lp, hipStream_t s, int grid);

@@ -845,10 +845,12 @@ hipError_t launch_sort_hist(Ctrl* ctrl, int buf, const uint32_t* R, const ulongl
 // ================================================================ group sort
 // After the Clifford layer the operator is still ordered by x-group; only the
 // z order inside each group is lost (every z of a group was XORed with the
-// same mask).  When no group exceeds kGsMaxGroup strings, each group is
-// sorted by z inside one workgroup: a string's new position is its group's
-// start plus the number of group members with a smaller z (z values within a
-// group are distinct).  Groups keep their positions, so no prefix sum across
+// same mask).  The same holds after a general rotation with x_J = 0, whose
+// children stay in their parent's group.  When no group exceeds kGsMaxGroup
+// strings, each group is sorted by z inside one workgroup: a string's new
+// position is its group's start plus the number of group members with a
+// smaller z, equal z counting for the members before it (a stable order, so
+// the duplicate keys a rotation creates land next to each other).  Groups keep their positions, so no prefix sum across
 // workgroups is needed.  Workgroup tiles cover kGsTile positions and own the
 // groups that start there.  A group that would not fit sets ctrl->aux[2] and
 // the caller falls back to the radix sort (the input is left untouched).
@@ -926,9 +928,9 @@ __global__ __launch_bounds__(kGsThreads) void k_group_sort(GroupSortArgs A) {
             if (e >= m) continue;
             const ulonglong2 z = zr[k];
             uint32_t r = 0, j = e;
-            while (!sF[j]) {  // members before e in the group
+            while (!sF[j]) {  // members before e in the group (ties count: stable)
                 --j;
-                r += k_lt(sZ[j], z);
+                r += k_le(sZ[j], z);
             }
             const uint32_t gs = j;
             for (j = e + 1; !sF[j]; ++j) r += k_lt(sZ[j], z);  // members after e

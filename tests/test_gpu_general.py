@@ -137,3 +137,30 @@ def test_general_gate_capacity_growth():
     g.apply_rotation_layer(gate)
     o.apply(gate)
     assert_same_operator(g, o, coeff_exact=True)
+
+
+def test_z_only_rotation_inside_an_rx_run_keeps_the_stream():
+    """A non-Clifford RZZ between RX gates: the general path keeps the stored x
+    rotation (children stay in their x-group), sorts inside the groups, and
+    the RX run continues on its streaming path; against the oracle, and a
+    large x-group forces the radix-sort fallback of the same stage."""
+    n = 14
+    terms, coeffs = w.random_pauli_set(n, 3000, seed=51)
+    def rot(ops, th):
+        return w.pauli_words(n, ops), th
+    seq = [rot({0: "X"}, 0.3), rot({1: "X"}, 0.4), rot({2: "Z", 5: "Z"}, 0.7), rot({2: "X"}, 0.5),
+           rot({3: "X"}, 0.6), rot({6: "Z"}, 1.1), rot({4: "X"}, 0.2)]
+    gl = w.GateList(np.stack([s[0] for s in seq]), np.array([[s[1]] for s in seq]))
+    for label, tt, cc in (("random set", terms, coeffs),
+                          ("Z-only set (one x-group of 4000+)",
+                           *w.random_pauli_set(n, 6000, seed=52))):
+        if label.startswith("Z-only"):
+            tt = tt.copy()
+            tt[:, :2] = 0  # x = 0 for every string: a single x-group
+            tt, idx = np.unique(tt, axis=0, return_index=True)
+            cc = cc[idx]
+        g, o = _both(n, tt, cc)
+        g.apply_rotation_layer(gl, 1e-6)
+        o.apply(gl, 1e-6)
+        say(f"{label}: |O| = {g.size()}")
+        assert_same_operator(g, o, coeff_exact=True)
