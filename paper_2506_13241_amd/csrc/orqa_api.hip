@@ -160,6 +160,9 @@ struct ps_handle {
     };
     std::vector<GraphEntry> graph_cache;
     double graph_replays = 0, graph_captures = 0;
+    // general gates with x_J = 0: after a group sort that overflowed, the next
+    // gs_skip such gates go straight to the radix sort
+    int gs_skip = 0;
 };
 
 namespace {
@@ -625,7 +628,9 @@ int run_rx_graph(ps_handle* h, const std::vector<GateTrig>& trigs, double pend0,
 
 // Re-sort buffer `b` (front only, with group ranks) by (rank, z).  Returns the
 // buffer holding the result in *result.
-int sort_by_rank_z(ps_handle* h, int b, int* result, bool full_key = false, bool try_groups = true) {
+int sort_by_rank_z(ps_handle* h, int b, int* result, bool full_key = false, bool try_groups = true,
+                   bool* overflowed = nullptr) {
+    if (overflowed) *overflowed = false;
     Ctrl c;
     int rc = read_ctrl(h, &c);
     if (rc) return rc;
@@ -660,6 +665,7 @@ int sort_by_rank_z(ps_handle* h, int b, int* result, bool full_key = false, bool
             return PS_OK;
         }
         // a group too large for one workgroup: radix sort from the untouched input
+        if (overflowed) *overflowed = true;
         const uint64_t zero = 0;
         HIP_TRY(hipMemcpyAsync(&h->ctrl->aux[2], &zero, 8, hipMemcpyHostToDevice, h->stream));
         HIP_TRY(hipMemcpyAsync(&h->ctrl->nf[1 - b], &zero, 8, hipMemcpyHostToDevice, h->stream));
@@ -1168,7 +1174,11 @@ int apply_rotation_layer(ps_handle* h, const ps_pauli* gens, const double* theta
             int res = h->cur;
             // x_J = 0: outputs stay in their x-groups, which keep their order:
             // sort inside the groups; otherwise the full (x, z) radix sort
-            rc = sort_by_rank_z(h, h->cur, &res, true, gen_zonly);
+            const bool try_groups = gen_zonly && h->gs_skip == 0;
+            if (gen_zonly && h->gs_skip > 0) --h->gs_skip;
+            bool over = false;
+            rc = sort_by_rank_z(h, h->cur, &res, true, try_groups, &over);
+            if (over) h->gs_skip = 32;
             if (rc) return rc;
             rc = enqueue_gen_reduce(h, res, 1 - res, 1 - mx_branch);
             if (rc) return rc;
