@@ -173,6 +173,19 @@ int pauli_sum_export(ps_handle* h, ps_pauli* keys, void* coeffs, size_t cap, siz
  *                       may be destroyed afterwards).
  */
 /*
+ * pauli_sum_histogram -- the Pauli-string density of Appendix D: counts of the
+ * coefficients of lane `lane` rescaled by their largest magnitude,
+ * x = O_I / max_I |O_I| (is_signed != 0) or |O_I| / max_I |O_I| (is_signed == 0),
+ * over the bins [edges[k], edges[k+1]) for k < n_bins - 1 and the closed last
+ * bin [edges[n_bins-1], edges[n_bins]].  edges (host, n_bins + 1 values,
+ * strictly increasing, 1 <= n_bins <= 4096); bin membership is decided by
+ * comparing the coefficient with max|O| * edges[k] in binary64.  counts (host
+ * out, n_bins + 2): the bins, then the values below edges[0], then those above
+ * edges[n_bins].  Applies a pending truncation first (as export does).
+ */
+int pauli_sum_histogram(ps_handle* h, int lane, const double* edges, int n_bins, int is_signed, uint64_t* counts);
+
+/*
  * pauli_sum_set_graphs -- with enable != 0, every run of consecutive RX gates
  * in a layer (e.g. the RX half of a Trotter step) is captured once into a HIP
  * graph and replayed when the same gates meet the same buffers again, so a

@@ -27,6 +27,7 @@ EXPORTED_SYMBOLS = (
     "pauli_sum_load_scorer", "pauli_sum_set_timing", "pauli_sum_stats", "ps_last_error",
     "ps_scorer_create", "ps_scorer_destroy", "ps_scorer_set_params", "ps_scorer_get_params", "ps_scorer_set_data",
     "ps_scorer_forward", "ps_scorer_loss_grad", "ps_scorer_adam_step", "pauli_sum_set_graphs",
+    "pauli_sum_histogram",
 )
 N_SCORER_PARAMS = 37249
 
@@ -82,6 +83,7 @@ def load_library(path: str = LIB_PATH):
         "pauli_sum_stats": (I, [P, ctypes.POINTER(ps_stats), I]),
         "ps_last_error": (ctypes.c_char_p, []),
         "pauli_sum_set_graphs": (I, [P, I]),
+        "pauli_sum_histogram": (I, [P, I, P, I, I, P]),
         "ps_scorer_create": (I, [I, P, P, P, P, ctypes.POINTER(P)]),
         "ps_scorer_destroy": (I, [P]),
         "ps_scorer_set_params": (I, [P, P, S]),
@@ -214,6 +216,23 @@ class PauliSum:
         t, c = self.export()
         return {tuple(int(v) for v in row): c[i].copy() for i, row in enumerate(t)}
 
+    def histogram(self, edges, signed: bool = True, lane: int = 0) -> np.ndarray:
+        """Counts over the bins given by `edges` (relative to max|c|), then the
+        counts below and above the range (Pauli-string density, Appendix D)."""
+        e = np.ascontiguousarray(edges, dtype=np.float64)
+        out = np.zeros(e.size + 1, dtype=np.uint64)
+        _check(_lib.pauli_sum_histogram(self._h, lane, _ptr(e), e.size - 1, int(signed), _ptr(out)))
+        return out
+
+    def density(self, n_bins: int = 200, signed: bool = True, lane: int = 0):
+        """D_t(x): normalized histogram of x = c / max|c| on [-1, 1] (signed) or
+        [0, 1]; returns (bin centres, density)."""
+        edges = np.linspace(-1.0 if signed else 0.0, 1.0, n_bins + 1)
+        cnt = self.histogram(edges, signed, lane)[:n_bins].astype(np.float64)
+        width = edges[1] - edges[0]
+        total = cnt.sum()
+        return 0.5 * (edges[1:] + edges[:-1]), (cnt / (total * width) if total else cnt)
+
     def load_scorer(self, scorer: "PsScorer"):
         """Copy a scorer's network into this handle (for PS_TRUNC_LEARNED)."""
         _check(_lib.pauli_sum_load_scorer(self._h, scorer._h))
@@ -317,6 +336,10 @@ def pauli_sum_norm2(ps: PauliSum):
 
 def pauli_sum_export(ps: PauliSum):
     return ps.export()
+
+
+def pauli_sum_histogram(ps: PauliSum, edges, signed=True, lane=0):
+    return ps.histogram(edges, signed, lane)
 
 
 def pauli_sum_load_scorer(ps: PauliSum, scorer: PsScorer):

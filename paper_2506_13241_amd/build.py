@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liborqa_hip.so")
-SOURCES = ["orqa_kernels.hip", "orqa_general.hip", "orqa_scorer.hip", "orqa_api.hip", "orqa_scorer_api.hip"]
+SOURCES = ["orqa_kernels.hip", "orqa_general.hip", "orqa_diag.hip", "orqa_scorer.hip", "orqa_api.hip", "orqa_scorer_api.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

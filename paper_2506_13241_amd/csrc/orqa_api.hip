@@ -1378,6 +1378,53 @@ int pauli_sum_stats(ps_handle* h, ps_stats* out, int reset) {
     return PS_OK;
 }
 
+int pauli_sum_histogram(ps_handle* h, int lane, const double* edges, int n_bins, int is_signed, uint64_t* counts) {
+    if (!h || !edges || !counts) return fail(PS_ERR_INVALID, "NULL argument");
+    if (h->broken) return fail(PS_ERR_DEVICE, "handle is no longer usable");
+    if (lane < 0 || lane >= h->L) return fail(PS_ERR_INVALID, "lane %d out of range", lane);
+    if (n_bins < 1 || n_bins > kHistMaxBins) return fail(PS_ERR_INVALID, "n_bins must be in 1..%d", kHistMaxBins);
+    for (int k = 0; k <= n_bins; ++k) {
+        if (!std::isfinite(edges[k])) return fail(PS_ERR_NONFINITE, "edge %d is not finite", k);
+        if (k > 0 && !(edges[k] > edges[k - 1])) return fail(PS_ERR_INVALID, "edges must increase");
+    }
+    int rc = materialize(h);
+    if (rc) return rc;
+    Ctrl c;
+    rc = read_ctrl(h, &c);
+    if (rc) return rc;
+    double M;
+    std::memcpy(&M, &c.maxbits[h->mx][lane], 8);
+    std::vector<double> t(n_bins + 1);
+    for (int k = 0; k <= n_bins; ++k) t[k] = M * edges[k];
+    double* dT = nullptr;
+    uint64_t* dC = nullptr;
+    if (hipMalloc(reinterpret_cast<void**>(&dT), t.size() * 8) != hipSuccess ||
+        hipMalloc(reinterpret_cast<void**>(&dC), (n_bins + 2) * 8) != hipSuccess) {
+        (void)hipGetLastError();
+        if (dT) (void)hipFree(dT);
+        return fail(PS_ERR_CAPACITY, "hipMalloc failed for the histogram");
+    }
+    HistArgs a{};
+    a.ctrl = h->ctrl;
+    a.buf = h->cur;
+    a.C = h->buf[h->cur].C;
+    a.cap = h->cap;
+    a.lane = lane;
+    a.nbins = n_bins;
+    a.is_signed = is_signed ? 1 : 0;
+    a.thresholds = dT;
+    a.counts = dC;
+    hipError_t e = hipMemcpyAsync(dT, t.data(), t.size() * 8, hipMemcpyHostToDevice, h->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(dC, 0, (n_bins + 2) * 8, h->stream);
+    if (e == hipSuccess) e = launch_histogram(a, h->dtype, h->LP, h->stream, h->grid);
+    if (e == hipSuccess) e = hipMemcpyAsync(counts, dC, (n_bins + 2) * 8, hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    (void)hipFree(dT);
+    (void)hipFree(dC);
+    if (e != hipSuccess) return fail(PS_ERR_HIP, "histogram: %s", hipGetErrorString(e));
+    return PS_OK;
+}
+
 int pauli_sum_set_graphs(ps_handle* h, int enable) {
     if (!h) return fail(PS_ERR_INVALID, "NULL argument");
     if (h->broken) return fail(PS_ERR_DEVICE, "handle is no longer usable");

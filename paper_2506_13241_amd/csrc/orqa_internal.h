@@ -194,6 +194,19 @@ struct GenArgs {
 hipError_t launch_gen_branch(const GenArgs& a, const GateTrig& g, int dtype, int lp, hipStream_t s, int grid);
 hipError_t launch_gen_reduce(const GenArgs& a, int dtype, int lp, hipStream_t s, int grid);
 
+// Coefficient histogram (Pauli-string density, Appendix D).
+constexpr int kHistMaxBins = 4096;
+struct HistArgs {
+    const Ctrl* ctrl;
+    int buf;
+    const void* C;
+    uint64_t cap;
+    int lane, nbins, is_signed;
+    const double* thresholds;  // nbins + 1, increasing
+    uint64_t* counts;          // nbins + 2
+};
+hipError_t launch_histogram(const HistArgs& a, int dtype, int lp, hipStream_t s, int grid);
+
 #define ORQA_DISPATCH(DTYPE, LP, F)                      \
     do {                                                 \
         if ((DTYPE) == 0) {                              \
