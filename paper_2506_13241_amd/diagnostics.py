@@ -1,0 +1,137 @@
+"""Diagnostics of a propagation run, as the paper reports them (Fig. 2, Fig. 5).
+
+    python -m paper_2506_13241_amd.diagnostics curves --theta-pi 0.1 --eps 1e-4 --steps 20
+    python -m paper_2506_13241_amd.diagnostics sweep --eps 1e-2 --steps 20 --angles 32
+
+curves: per Trotter step t of the 127-qubit kicked Ising circuit, <M_t> (the
+  observable's expectation, Eq. magnetization), the effective complexity |O|
+  (Eq. define_O), the wall time of the step and, with --density-bins B, the
+  Pauli-string density D_t(x) (Appendix D) over B bins of log10 |x|,
+  x = O_I / max|O_I|, from log10(eps) - 1 to 0 (the truncation edge at
+  log10 eps then shows as the sharp cutoff of Fig. 5).
+sweep: <M_t> at the last step for `angles` values of theta_x uniform in
+  [0, pi/2], all carried as coefficient lanes of one operator (one key path
+  for every angle; the truncation threshold is taken on the largest
+  coefficient over the lanes, so each lane keeps a superset of what a run of
+  its own would keep), plus the shared |O|.  With --per-angle every angle runs
+  on its own instead, which gives each angle's own |O| as in Fig. 2e.
+
+One JSON object per line on stdout.  A step that needs more device memory than
+the GPU holds ends the run with a line {"stopped": ...}.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import sys
+import time
+
+import numpy as np
+
+import workload as w
+
+from . import PauliSum, PsError, load_library
+
+
+def _lattice(name):
+    return w.eagle_127() if name == "eagle127" else w.heavy_hex_21()
+
+
+def log_density_edges(eps: float, bins: int) -> np.ndarray:
+    """Edges in |x| spaced evenly in log10 from eps/10 to 1."""
+    return np.logspace(math.log10(eps) - 1.0, 0.0, bins + 1)
+
+
+def run_curves(lat, obs, theta_x, eps, steps, theta_zz=-math.pi / 2, dtype=0, density_bins=0, emit=print):
+    zz, rx = w.kicked_ising_step(lat, theta_x, theta_zz)
+    op = PauliSum(lat.n, *w.single_pauli_term(lat.n, {obs: "Z"}), dtype=dtype)
+    rows = []
+    try:
+        for t in range(1, steps + 1):
+            t0 = time.perf_counter()
+            try:
+                op.apply_rotation_layer(zz, eps).apply_rotation_layer(rx, eps)
+                m = float(op.expectation_z()[0])
+            except PsError as e:
+                emit(json.dumps({"stopped": t, "reason": str(e)}))
+                break
+            row = {"t": t, "M": m, "size": op.size(), "seconds": time.perf_counter() - t0}
+            if density_bins and eps > 0:
+                edges = log_density_edges(eps, density_bins)
+                cnt = op.histogram(edges, signed=False)
+                row["log10_x_edges"] = [float(v) for v in np.log10(edges)]
+                row["counts"] = [int(v) for v in cnt[:density_bins]]
+                row["below"], row["above"] = int(cnt[density_bins]), int(cnt[density_bins + 1])
+            rows.append(row)
+            emit(json.dumps(row))
+    finally:
+        op.close()
+    return rows
+
+
+def run_sweep(lat, obs, angles, eps, steps, theta_zz=-math.pi / 2, per_angle=False, dtype=1, emit=print):
+    thetas = np.linspace(0.0, math.pi / 2, angles)
+    if per_angle:
+        out = []
+        for th in thetas:
+            rows = run_curves(lat, obs, float(th), eps, steps, theta_zz, dtype, emit=lambda s: None)
+            last = rows[-1] if rows else {"t": 0, "M": float("nan"), "size": 0}
+            row = {"theta_x": float(th), "t": last["t"], "M": last["M"], "size": last["size"]}
+            out.append(row)
+            emit(json.dumps(row))
+        return out
+    zz, rx = w.kicked_ising_step(lat, thetas, theta_zz, lanes=angles)
+    op = PauliSum(lat.n, *w.single_pauli_term(lat.n, {obs: "Z"}, lanes=angles), dtype=dtype)
+    try:
+        t_done = 0
+        for t in range(1, steps + 1):
+            try:
+                op.apply_rotation_layer(zz, eps).apply_rotation_layer(rx, eps)
+            except PsError as e:
+                emit(json.dumps({"stopped": t, "reason": str(e)}))
+                break
+            t_done = t
+            print(json.dumps({"t": t, "size": op.size()}), file=sys.stderr, flush=True)
+        m = op.expectation_z() if t_done else np.full(angles, np.nan)
+        row = {"t": t_done, "size": op.size(), "theta_x": [float(v) for v in thetas], "M": [float(v) for v in m]}
+        emit(json.dumps(row))
+        return row
+    finally:
+        op.close()
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    for name in ("curves", "sweep"):
+        p = sub.add_parser(name)
+        p.add_argument("--lattice", default="eagle127", choices=["eagle127", "patch21"])
+        p.add_argument("--obs", type=int, default=None)
+        p.add_argument("--eps", type=float, default=1e-4)
+        p.add_argument("--steps", type=int, default=20)
+        p.add_argument("--theta-zz", type=float, default=-math.pi / 2)
+        p.add_argument("--dtype", choices=["f64", "f32"], default="f64" if name == "curves" else "f32")
+        if name == "curves":
+            p.add_argument("--theta-pi", type=float, default=0.1, help="theta_x in units of pi")
+            p.add_argument("--density-bins", type=int, default=0)
+        else:
+            p.add_argument("--angles", type=int, default=32)
+            p.add_argument("--per-angle", action="store_true")
+    a = ap.parse_args(argv)
+    load_library()
+    lat = _lattice(a.lattice)
+    obs = lat.center if a.obs is None else a.obs
+    if a.cmd == "curves":
+        run_curves(lat, obs, a.theta_pi * math.pi, a.eps, a.steps, a.theta_zz,
+                   0 if a.dtype == "f64" else 1, a.density_bins)
+    else:
+        if not 1 <= a.angles <= 32:
+            ap.error("--angles must be in 1..32")
+        run_sweep(lat, obs, a.angles, a.eps, a.steps, a.theta_zz, a.per_angle, 0 if a.dtype == "f64" else 1)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())
