@@ -186,6 +186,20 @@ int pauli_sum_export(ps_handle* h, ps_pauli* keys, void* coeffs, size_t cap, siz
 int pauli_sum_histogram(ps_handle* h, int lane, const double* edges, int n_bins, int is_signed, uint64_t* counts);
 
 /*
+ * pauli_sum_set_sort_config -- digit width and tile size of the radix sort
+ * (the re-sort after a Clifford layer, Eq. (u), when its x-groups are too large
+ * for the in-group sort, and the merge of general gates, Eq. update_rule).
+ * (digit_bits, items_per_thread) is one of (8, 8), (8, 16), (7, 16), (6, 16),
+ * (7, 8), (6, 8); a tile holds 256 * items_per_thread strings.  (0, 0), the
+ * default, tunes online: the first sorts of each size class (powers of two of
+ * the string count, from 2^16) and key kind time each configuration once, and
+ * later sorts of that class use the fastest.  Every configuration sorts the
+ * same keys into the same order, so results do not depend on this setting.
+ * Errors: PS_ERR_INVALID for any other pair.
+ */
+int pauli_sum_set_sort_config(ps_handle* h, int digit_bits, int items_per_thread);
+
+/*
  * pauli_sum_set_graphs -- with enable != 0, every run of consecutive RX gates
  * in a layer (e.g. the RX half of a Trotter step) is captured once into a HIP
  * graph and replayed when the same gates meet the same buffers again, so a
@@ -226,6 +240,10 @@ int pauli_sum_load_scorer(ps_handle* h, const ps_scorer* s);
  *                  into HIP graphs (pauli_sum_set_graphs)
  *   score_launches, score_in, score_ms  learned-scorer launches, strings
  *                  scored and their kernel time (PS_TRUNC_LEARNED)
+ *   radix_sorts    radix sorts run (re-sorts whose x-groups did not fit the
+ *                  in-group sort, and sorts of general gates);
+ *                  sort_digit_bits, sort_items_per_thread the configuration
+ *                  of the last one (pauli_sum_set_sort_config)
  */
 typedef struct {
     double updates, gates;
@@ -235,6 +253,7 @@ typedef struct {
     double bytes_per_string;
     double graph_replays, graph_captures;
     double score_launches, score_in, score_ms;
+    double radix_sorts, sort_digit_bits, sort_items_per_thread;
 } ps_stats;
 
 int pauli_sum_set_timing(ps_handle* h, int enable);

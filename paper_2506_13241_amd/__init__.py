@@ -27,9 +27,10 @@ EXPORTED_SYMBOLS = (
     "pauli_sum_load_scorer", "pauli_sum_set_timing", "pauli_sum_stats", "ps_last_error",
     "ps_scorer_create", "ps_scorer_destroy", "ps_scorer_set_params", "ps_scorer_get_params", "ps_scorer_set_data",
     "ps_scorer_forward", "ps_scorer_loss_grad", "ps_scorer_adam_step", "pauli_sum_set_graphs",
-    "pauli_sum_histogram",
+    "pauli_sum_histogram", "pauli_sum_set_sort_config",
 )
 N_SCORER_PARAMS = 37249
+SORT_CONFIGS = ((8, 8), (8, 16), (7, 16), (6, 16), (7, 8), (6, 8))  # (digit bits, items per thread)
 
 
 class PsError(RuntimeError):
@@ -46,7 +47,8 @@ class ps_stats(ctypes.Structure):
     _fields_ = [(name, ctypes.c_double) for name in (
         "updates", "gates", "rx_launches", "rx_in", "rx_out", "rx_ms", "cliff_launches", "cliff_in", "cliff_ms",
         "sort_passes", "sort_elems", "sort_ms", "bytes_per_string", "graph_replays", "graph_captures",
-        "score_launches", "score_in", "score_ms")]
+        "score_launches", "score_in", "score_ms",
+        "radix_sorts", "sort_digit_bits", "sort_items_per_thread")]
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -84,6 +86,7 @@ def load_library(path: str = LIB_PATH):
         "ps_last_error": (ctypes.c_char_p, []),
         "pauli_sum_set_graphs": (I, [P, I]),
         "pauli_sum_histogram": (I, [P, I, P, I, I, P]),
+        "pauli_sum_set_sort_config": (I, [P, I, I]),
         "ps_scorer_create": (I, [I, P, P, P, P, ctypes.POINTER(P)]),
         "ps_scorer_destroy": (I, [P]),
         "ps_scorer_set_params": (I, [P, P, S]),
@@ -205,6 +208,11 @@ class PauliSum:
 
     def set_graphs(self, enable: bool = True):
         _check(_lib.pauli_sum_set_graphs(self._h, int(enable)))
+        return self
+
+    def set_sort_config(self, digit_bits: int = 0, items_per_thread: int = 0):
+        """Radix-sort digit width and tile size; (0, 0) tunes online."""
+        _check(_lib.pauli_sum_set_sort_config(self._h, int(digit_bits), int(items_per_thread)))
         return self
 
     def stats(self, reset: bool = False) -> dict:

@@ -163,6 +163,14 @@ struct ps_handle {
     // general gates with x_J = 0: after a group sort that overflowed, the next
     // gs_skip such gates go straight to the radix sort
     int gs_skip = 0;
+    // radix-sort configuration: forced by pauli_sum_set_sort_config, or tuned
+    // online (each candidate timed once per key kind and size class, then
+    // the fastest kept); every configuration gives the same result
+    int sort_force = -1;  // candidate index, -1: tune
+    float sort_ns[2][64][6] = {};  // ns per string, 0: not tried yet
+    hipEvent_t sort_ev[2] = {nullptr, nullptr};
+    int sort_last = 0;
+    double radix_sorts = 0;
 };
 
 namespace {
@@ -628,6 +636,41 @@ int run_rx_graph(ps_handle* h, const std::vector<GateTrig>& trigs, double pend0,
 
 // Re-sort buffer `b` (front only, with group ranks) by (rank, z).  Returns the
 // buffer holding the result in *result.
+// Radix-sort candidates: (digit bits, items per thread).  Narrower digits
+// give longer runs per bucket in each tile (better write coalescing) at the
+// price of more passes; larger tiles do the same for fewer look-back steps.
+constexpr int kSortCands = 6;
+constexpr int kSortCandBits[kSortCands] = {8, 8, 7, 6, 7, 6};
+constexpr int kSortCandIpt[kSortCands] = {8, 16, 16, 16, 8, 8};
+constexpr uint64_t kSortTuneMin = 1u << 16;  // smaller sorts use candidate 0 untimed
+
+SortPlan make_sort_plan(int nq, bool full_key, int rbits, int bits) {
+    SortPlan p{};
+    auto seg = [&](int base, int len) {
+        for (int o = 0; o < len; o += bits) {
+            p.lo[p.npass] = static_cast<uint16_t>(base + o);
+            p.w[p.npass] = static_cast<uint8_t>(std::min(bits, len - o));
+            ++p.npass;
+        }
+    };
+    seg(0, nq);                          // z, least significant
+    if (full_key) seg(192, nq);          // then x
+    else seg(128, rbits);                // or the x-group rank
+    return p;
+}
+
+int pick_sort_candidate(const ps_handle* h, int kind, int cls, uint64_t n) {
+    if (h->sort_force >= 0) return h->sort_force;
+    if (n < kSortTuneMin) return 0;
+    const float* t = h->sort_ns[kind][cls];
+    int best = 0;
+    for (int c = 0; c < kSortCands; ++c) {
+        if (t[c] == 0.0f) return c;  // not tried in this class yet
+        if (t[c] < t[best]) best = c;
+    }
+    return best;
+}
+
 int sort_by_rank_z(ps_handle* h, int b, int* result, bool full_key = false, bool try_groups = true,
                    bool* overflowed = nullptr) {
     if (overflowed) *overflowed = false;
@@ -670,45 +713,60 @@ int sort_by_rank_z(ps_handle* h, int b, int* result, bool full_key = false, bool
         HIP_TRY(hipMemcpyAsync(&h->ctrl->aux[2], &zero, 8, hipMemcpyHostToDevice, h->stream));
         HIP_TRY(hipMemcpyAsync(&h->ctrl->nf[1 - b], &zero, 8, hipMemcpyHostToDevice, h->stream));
     }
-    HIP_TRY(hipMemsetAsync(h->hist, 0, kSortDigits * 256 * sizeof(uint32_t), h->stream));
-    HIP_TRY(launch_sort_hist(h->ctrl, b, h->rank[b], h->buf[b].Z, h->buf[b].X, full_key ? 1 : 0, h->hist, h->stream,
-                             h->grid));
-    std::vector<uint32_t> hist(kSortDigits * 256);
+    const int kind = full_key ? 1 : 0;
+    int cls = 0;
+    while (cls < 63 && (uint64_t(2) << cls) <= n) ++cls;
+    const int cand = pick_sort_candidate(h, kind, cls, n);
+    const int bits = kSortCandBits[cand], ipt = kSortCandIpt[cand];
+    int rbits = 32;
+    if (!full_key && c.nranks > 0 && c.nranks <= (uint64_t(1) << 32)) {
+        rbits = 1;
+        while (rbits < 32 && (uint64_t(1) << rbits) < c.nranks) ++rbits;
+    }
+    const SortPlan plan = make_sort_plan(h->nq, full_key, rbits, bits);
+    HIP_TRY(hipMemsetAsync(h->hist, 0, kSortMaxPasses * 256 * sizeof(uint32_t), h->stream));
+    HIP_TRY(launch_sort_hist(h->ctrl, b, full_key ? nullptr : h->rank[b], h->buf[b].Z, h->buf[b].X, plan, h->hist,
+                             h->stream, h->grid));
+    std::vector<uint32_t> hist(plan.npass * 256);
     HIP_TRY(hipMemcpyAsync(hist.data(), h->hist, hist.size() * sizeof(uint32_t), hipMemcpyDeviceToHost, h->stream));
     HIP_TRY(hipStreamSynchronize(h->stream));
-    std::vector<int> digits;
-    for (int d = 0; d < kSortDigits; ++d) {
-        if (d < 16 && 8 * (d & 7) + 64 * (d >> 3) >= h->nq) continue;  // z byte above the register
-        if (full_key ? (d >= 16 && d < 20) : d >= 20) continue;        // (x, z) or (rank, z)
-        if (d >= 20 && 8 * ((d - 20) & 7) + 64 * ((d - 20) >> 3) >= h->nq) continue;  // x byte above
+    std::vector<int> passes;  // plan entries whose digit is not constant
+    for (int p = 0; p < plan.npass; ++p) {
         int nonzero = 0;
-        for (int k = 0; k < 256; ++k) nonzero += hist[d * 256 + k] != 0;
-        if (nonzero > 1) digits.push_back(d);
+        for (int k = 0; k < 256; ++k) nonzero += hist[p * 256 + k] != 0;
+        if (nonzero > 1) passes.push_back(p);
     }
-    if (digits.empty()) return PS_OK;
-    std::vector<uint32_t> bases(digits.size() * 256);
-    for (size_t i = 0; i < digits.size(); ++i) {
+    if (passes.empty()) return PS_OK;
+    std::vector<uint32_t> bases(passes.size() * 256);
+    for (size_t i = 0; i < passes.size(); ++i) {
         uint64_t run = 0;
         for (int k = 0; k < 256; ++k) {
             bases[i * 256 + k] = static_cast<uint32_t>(run);
-            run += hist[digits[i] * 256 + k];
+            run += hist[passes[i] * 256 + k];
         }
     }
     HIP_TRY(hipMemcpyAsync(h->digit_base, bases.data(), bases.size() * sizeof(uint32_t), hipMemcpyHostToDevice,
                            h->stream));
+    const bool tune = h->sort_force < 0 && n >= kSortTuneMin;
+    if (tune && !h->sort_ev[0]) {
+        HIP_TRY(hipEventCreate(&h->sort_ev[0]));
+        HIP_TRY(hipEventCreate(&h->sort_ev[1]));
+    }
+    if (tune) HIP_TRY(hipEventRecord(h->sort_ev[0], h->stream));
     int src = b;
-    for (size_t i = 0; i < digits.size(); ++i) {
+    for (size_t i = 0; i < passes.size(); ++i) {
         const int dst = 1 - src;
         SortPassArgs a{};
         a.ctrl = h->ctrl;
         a.n = n;
-        a.digit = digits[i];
+        a.lo = plan.lo[passes[i]];
+        a.w = plan.w[passes[i]];
         a.digit_base = h->digit_base + i * 256;
-        a.Rs = h->rank[src];
+        a.Rs = full_key ? nullptr : h->rank[src];
         a.Zs = h->buf[src].Z;
         a.Xs = h->buf[src].X;
         a.Cs = h->buf[src].C;
-        a.Rd = h->rank[dst];
+        a.Rd = full_key ? nullptr : h->rank[dst];
         a.Zd = h->buf[dst].Z;
         a.Xd = h->buf[dst].X;
         a.Cd = h->buf[dst].C;
@@ -718,16 +776,26 @@ int sort_by_rank_z(ps_handle* h, int b, int* result, bool full_key = false, bool
         size_t slot;
         rc = ev_begin(h, 2, &slot);
         if (rc) return rc;
-        HIP_TRY(launch_sort_pass(a, h->dtype, h->LP, h->stream, h->grid));
+        HIP_TRY(launch_sort_pass(a, ipt, h->dtype, h->LP, h->stream, h->grid));
         rc = ev_end(h, slot);
         if (rc) return rc;
         h->sort_passes += 1;
         h->sort_elems += double(n);
         src = dst;
     }
+    if (tune) HIP_TRY(hipEventRecord(h->sort_ev[1], h->stream));
     *result = src;
     // keep the host copy of the digit bases alive until the copy has run
     HIP_TRY(hipStreamSynchronize(h->stream));
+    h->radix_sorts += 1;
+    h->sort_last = cand;
+    if (tune) {
+        float ms = 0.0f;
+        HIP_TRY(hipEventElapsedTime(&ms, h->sort_ev[0], h->sort_ev[1]));
+        const float ns = std::max(1e-6f, ms * 1e6f / float(n));
+        float& slot = h->sort_ns[kind][cls][cand];
+        slot = (slot == 0.0f) ? ns : std::min(slot, ns);
+    }
     return ev_collect(h);
 }
 
@@ -847,8 +915,8 @@ int pauli_sum_create(int n_qubits, int n_lanes, int dtype, size_t capacity, cons
         return code;
     };
     if (hipMalloc(reinterpret_cast<void**>(&h->ctrl), sizeof(Ctrl)) != hipSuccess ||
-        hipMalloc(reinterpret_cast<void**>(&h->hist), kSortDigits * 256 * sizeof(uint32_t)) != hipSuccess ||
-        hipMalloc(reinterpret_cast<void**>(&h->digit_base), kSortDigits * 256 * sizeof(uint32_t)) != hipSuccess ||
+        hipMalloc(reinterpret_cast<void**>(&h->hist), kSortMaxPasses * 256 * sizeof(uint32_t)) != hipSuccess ||
+        hipMalloc(reinterpret_cast<void**>(&h->digit_base), kSortMaxPasses * 256 * sizeof(uint32_t)) != hipSuccess ||
         hipMalloc(reinterpret_cast<void**>(&h->partial), kReduceBlocks * kMaxLanes * sizeof(double)) != hipSuccess ||
         hipMalloc(reinterpret_cast<void**>(&h->red_out), kMaxLanes * sizeof(double)) != hipSuccess ||
         hipMalloc(reinterpret_cast<void**>(&h->cgens), kMaxCliffGens * sizeof(CliffGen)) != hipSuccess) {
@@ -902,6 +970,8 @@ int pauli_sum_destroy(ps_handle* h) {
     if (h->red_out) (void)hipFree(h->red_out);
     if (h->cgens) (void)hipFree(h->cgens);
     for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
+    for (hipEvent_t e : h->sort_ev)
+        if (e) (void)hipEventDestroy(e);
     if (h->has_scorer) scorer_free(&h->scorer);
     drop_graphs(h);
     if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
@@ -1362,7 +1432,11 @@ int pauli_sum_stats(ps_handle* h, ps_stats* out, int reset) {
     out->score_in = double(c.aux[0]);
     out->score_launches = double(c.aux[1]);
     out->score_ms = h->ms[3];
+    out->radix_sorts = h->radix_sorts;
+    out->sort_digit_bits = kSortCandBits[h->sort_last];
+    out->sort_items_per_thread = kSortCandIpt[h->sort_last];
     if (reset) {
+        h->radix_sorts = 0;
         h->graph_replays = h->graph_captures = 0;
         h->ms[3] = 0;
         const uint64_t z2[2] = {0, 0};
@@ -1423,6 +1497,22 @@ int pauli_sum_histogram(ps_handle* h, int lane, const double* edges, int n_bins,
     (void)hipFree(dC);
     if (e != hipSuccess) return fail(PS_ERR_HIP, "histogram: %s", hipGetErrorString(e));
     return PS_OK;
+}
+
+int pauli_sum_set_sort_config(ps_handle* h, int digit_bits, int items_per_thread) {
+    if (!h) return fail(PS_ERR_INVALID, "NULL argument");
+    if (digit_bits == 0 && items_per_thread == 0) {
+        h->sort_force = -1;
+        return PS_OK;
+    }
+    for (int c = 0; c < kSortCands; ++c) {
+        if (kSortCandBits[c] == digit_bits && kSortCandIpt[c] == items_per_thread) {
+            h->sort_force = c;
+            return PS_OK;
+        }
+    }
+    return fail(PS_ERR_INVALID, "no radix-sort configuration with %d-bit digits and %d items per thread", digit_bits,
+                items_per_thread);
 }
 
 int pauli_sum_set_graphs(ps_handle* h, int enable) {

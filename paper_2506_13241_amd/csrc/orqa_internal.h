@@ -24,9 +24,9 @@ constexpr int kRxTileMax = kThreads * kRxIPT;  // 768
 constexpr int kRxTile = kRxTileMax - 2;        // 766
 constexpr int kCompactIPT = 4;
 constexpr int kCompactTile = kThreads * kCompactIPT;  // 1024
-constexpr int kSortIPT = 8;
-constexpr int kSortTile = kThreads * kSortIPT;  // 2048
-constexpr int kSortDigits = 36;                 // 16 byte digits of z, 4 of the group rank, 16 of x
+constexpr int kSortIPT = 8;                     // smallest items per thread of a sort pass
+constexpr int kSortTile = kThreads * kSortIPT;  // 2048: smallest sort tile (sizes the status words)
+constexpr int kSortMaxPasses = 48;              // 2 x ceil(128 / 6) digits at the narrowest width
 constexpr int kReduceBlocks = 512;
 
 // Device-resident control block of a handle.  The two state buffers each hold
@@ -124,12 +124,21 @@ struct CompactArgs {
     double eps_learned;
 };
 
+// A radix-sort key is read as one integer whose 64-bit words, least
+// significant first, are z.x, z.y, the x-group rank, x.x, x.y; a digit is the
+// `w` bits (1..8) starting at bit `lo` of that integer.
+struct SortPlan {
+    int npass;
+    uint16_t lo[kSortMaxPasses];
+    uint8_t w[kSortMaxPasses];
+};
+
 struct SortPassArgs {
     Ctrl* ctrl;
     uint64_t n;
-    int digit;               // 0..15: byte of z (low word first), 16..19: byte of rank
-    const uint32_t* digit_base;  // 256 exclusive bucket starts for this digit
-    const uint32_t* Rs;
+    int lo, w;                   // digit bits [lo, lo + w) of the key
+    const uint32_t* digit_base;  // 2^w exclusive bucket starts for this digit
+    const uint32_t* Rs;          // NULL: no rank in the key (not moved either)
     const ulonglong2* Zs;
     const ulonglong2* Xs;
     const void* Cs;
@@ -147,8 +156,8 @@ hipError_t launch_rx_partition(const RxArgs& a, hipStream_t s);
 hipError_t launch_rx(const RxArgs& a, const GateTrig& g, int dtype, int lp, hipStream_t s, int grid);
 hipError_t launch_compact(const CompactArgs& a, int dtype, int lp, hipStream_t s, int grid);
 hipError_t launch_sort_hist(Ctrl* ctrl, int buf, const uint32_t* R, const ulonglong2* Z, const ulonglong2* X,
-                            int with_x, uint32_t* hist, hipStream_t s, int grid);
-hipError_t launch_sort_pass(const SortPassArgs& a, int dtype, int lp, hipStream_t s, int grid);
+                            const SortPlan& plan, uint32_t* hist, hipStream_t s, int grid);
+hipError_t launch_sort_pass(const SortPassArgs& a, int ipt, int dtype, int lp, hipStream_t s, int grid);
 
 // Re-sort after a Clifford layer when every x-group is small: each group is
 // sorted by z inside one workgroup, in place of the groups' positions.

@@ -622,54 +622,52 @@ __global__ __launch_bounds__(kThreads) void k_compact(CompactArgs A) {
 }
 
 // ================================================================ onesweep radix sort
-// Key = (rank, z1, z0) compared as an unsigned integer; LSD by 8-bit digits,
-// one stable pass per digit with decoupled look-back across tiles for the
-// 256 bucket offsets (Adinets & Merrill, "Onesweep", 2022).
+// LSD radix sort, one stable pass per digit, with decoupled look-back across
+// tiles for the bucket offsets (Adinets & Merrill, "Onesweep", 2022).  The
+// digit width (1..8 bits) and the tile size are chosen per sort by the host.
 
-// Digits of the radix sort, least significant first: 0..15 bytes of z (low
-// word first), 16..19 bytes of the x-group rank, 20..35 bytes of x.
-__device__ __forceinline__ uint32_t sort_digit(int digit, uint32_t r, const ulonglong2& z, const ulonglong2& x) {
-    if (digit < 8) return uint32_t(z.x >> (8 * digit)) & 0xFFu;
-    if (digit < 16) return uint32_t(z.y >> (8 * (digit - 8))) & 0xFFu;
-    if (digit < 20) return (r >> (8 * (digit - 16))) & 0xFFu;
-    if (digit < 28) return uint32_t(x.x >> (8 * (digit - 20))) & 0xFFu;
-    return uint32_t(x.y >> (8 * (digit - 28))) & 0xFFu;
+// Bits [lo, lo + w) of the key integer whose 64-bit words, least significant
+// first, are z.x, z.y, r, x.x, x.y.  A digit may straddle two words.
+__device__ __forceinline__ uint64_t key_word(int i, uint32_t r, const ulonglong2& z, const ulonglong2& x) {
+    return i == 0 ? z.x : i == 1 ? z.y : i == 2 ? uint64_t(r) : i == 3 ? x.x : x.y;
+}
+
+__device__ __forceinline__ uint32_t key_digit(int lo, int w, uint32_t r, const ulonglong2& z, const ulonglong2& x) {
+    const int i = lo >> 6, sh = lo & 63;
+    uint64_t v = key_word(i, r, z, x) >> sh;
+    if (sh + w > 64) v |= key_word(i + 1, r, z, x) << (64 - sh);
+    return uint32_t(v) & ((1u << w) - 1u);
 }
 
 __global__ __launch_bounds__(kThreads) void k_sort_hist(const Ctrl* __restrict__ ctrl, int buf,
                                                         const uint32_t* __restrict__ R,
                                                         const ulonglong2* __restrict__ Z,
-                                                        const ulonglong2* __restrict__ X, int with_x,
+                                                        const ulonglong2* __restrict__ X, SortPlan plan,
                                                         uint32_t* __restrict__ hist) {
-    __shared__ uint32_t sh[kSortDigits][256];
-    for (int i = threadIdx.x; i < kSortDigits * 256; i += kThreads) (&sh[0][0])[i] = 0;
+    __shared__ uint32_t sh[kSortMaxPasses][256];
+    const int np = plan.npass;
+    const bool need_x = np > 0 && plan.lo[np - 1] + plan.w[np - 1] > 192;  // passes ascend in lo
+    for (int i = threadIdx.x; i < np * 256; i += kThreads) (&sh[0][0])[i] = 0;
     __syncthreads();
     const uint64_t n = ctrl->nf[buf];
     if (!ctrl->err) {
         for (uint64_t i = blockIdx.x * uint64_t(kThreads) + threadIdx.x; i < n; i += uint64_t(gridDim.x) * kThreads) {
             const ulonglong2 z = Z[i];
-            if (with_x) {  // full key (x, z): z and x digits, no rank
-                const ulonglong2 x = X[i];
-#pragma unroll
-                for (int d = 0; d < 16; ++d) atomicAdd(&sh[d][sort_digit(d, 0, z, x)], 1u);
-#pragma unroll
-                for (int d = 20; d < kSortDigits; ++d) atomicAdd(&sh[d][sort_digit(d, 0, z, x)], 1u);
-            } else {  // (x-group rank, z)
-                const uint32_t r = R[i];
-#pragma unroll
-                for (int d = 0; d < 20; ++d) atomicAdd(&sh[d][sort_digit(d, r, z, z)], 1u);
-            }
+            const ulonglong2 x = need_x ? X[i] : ulonglong2{0, 0};
+            const uint32_t r = R ? R[i] : 0u;
+            for (int p = 0; p < np; ++p) atomicAdd(&sh[p][key_digit(plan.lo[p], plan.w[p], r, z, x)], 1u);
         }
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < kSortDigits * 256; i += kThreads) {
+    for (int i = threadIdx.x; i < np * 256; i += kThreads) {
         const uint32_t v = (&sh[0][0])[i];
         if (v) atomicAdd(hist + i, v);
     }
 }
 
-template <typename CT, int LP>
+template <typename CT, int LP, int IPT>
 __global__ __launch_bounds__(kThreads) void k_sort_pass(SortPassArgs A) {
+    constexpr int kTile = kThreads * IPT;
     __shared__ uint32_t sCnt[4][256];
     __shared__ uint64_t sOff[4][256];
     __shared__ uint32_t sTile;
@@ -678,9 +676,11 @@ __global__ __launch_bounds__(kThreads) void k_sort_pass(SortPassArgs A) {
     CT* __restrict__ Cd = static_cast<CT*>(A.Cd);
     const int tid = threadIdx.x, wave = tid >> 6, lane = lane_id();
     const bool skip = ctrl->err != 0u;
-    const uint64_t ntiles = skip ? 0 : (A.n + kSortTile - 1) / kSortTile;
+    const uint64_t ntiles = skip ? 0 : (A.n + kTile - 1) / kTile;
     const uint32_t ep = ctrl->epoch;
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    const int w = A.w, nbk = 1 << A.w;
+    const bool has_r = A.Rs != nullptr;
 
     for (;;) {
         const uint32_t tile = acquire_tile(ctrl, &sTile);
@@ -688,22 +688,23 @@ __global__ __launch_bounds__(kThreads) void k_sort_pass(SortPassArgs A) {
         for (int i = tid; i < 4 * 256; i += kThreads) (&sCnt[0][0])[i] = 0;
         __syncthreads();
         // warp-striped: wave w owns a contiguous segment of 64*IPT strings
-        const uint64_t seg = uint64_t(tile) * kSortTile + uint64_t(wave) * 64 * kSortIPT;
-        uint32_t dig[kSortIPT];
-        uint32_t loc[kSortIPT];
+        const uint64_t seg = uint64_t(tile) * kTile + uint64_t(wave) * 64 * IPT;
+        uint32_t dig[IPT];
+        uint32_t loc[IPT];
 #pragma unroll
-        for (int k = 0; k < kSortIPT; ++k) {
+        for (int k = 0; k < IPT; ++k) {
             const uint64_t i = seg + uint64_t(k) * 64 + lane;
             const bool valid = i < A.n;
             uint32_t d = 0;
-            if (valid) d = A.digit < 20 ? sort_digit(A.digit, A.Rs[i], A.Zs[i], A.Zs[i])
-                                         : sort_digit(A.digit, 0, A.Zs[i], A.Xs[i]);
+            if (valid) d = key_digit(A.lo, w, has_r ? A.Rs[i] : 0u, A.Zs[i], A.Xs[i]);
             dig[k] = valid ? d : 0xFFFFFFFFu;
             uint64_t peers = __ballot(valid);
 #pragma unroll
             for (int b = 0; b < 8; ++b) {
-                const uint64_t bb = __ballot((d >> b) & 1u);
-                peers &= ((d >> b) & 1u) ? bb : ~bb;
+                if (b < w) {
+                    const uint64_t bb = __ballot((d >> b) & 1u);
+                    peers &= ((d >> b) & 1u) ? bb : ~bb;
+                }
             }
             uint32_t pre = 0;
             if (valid) pre = sCnt[wave][d];
@@ -712,8 +713,8 @@ __global__ __launch_bounds__(kThreads) void k_sort_pass(SortPassArgs A) {
             if (valid && below == 0) sCnt[wave][d] = pre + __popcll(peers);
         }
         __syncthreads();
-        // per digit: prefix over waves, tile total, look-back across tiles
-        {
+        // per bucket: prefix over waves, tile total, look-back across tiles
+        if (tid < nbk) {
             const int d = tid;
             const uint32_t c0 = sCnt[0][d], c1 = sCnt[1][d], c2 = sCnt[2][d], c3 = sCnt[3][d];
             const uint32_t tot = c0 + c1 + c2 + c3;
@@ -726,12 +727,12 @@ __global__ __launch_bounds__(kThreads) void k_sort_pass(SortPassArgs A) {
         }
         __syncthreads();
 #pragma unroll
-        for (int k = 0; k < kSortIPT; ++k) {
+        for (int k = 0; k < IPT; ++k) {
             if (dig[k] == 0xFFFFFFFFu) continue;
             const uint64_t i = seg + uint64_t(k) * 64 + lane;
             const uint64_t o = sOff[wave][dig[k]] + loc[k];
             if (o >= A.n) continue;  // cannot happen for a consistent histogram
-            A.Rd[o] = A.Rs[i];
+            if (has_r) A.Rd[o] = A.Rs[i];
             A.Zd[o] = A.Zs[i];
             A.Xd[o] = A.Xs[i];
 #pragma unroll
@@ -837,8 +838,8 @@ hipError_t launch_compact(const CompactArgs& a, int dtype, int lp, hipStream_t s
 }
 
 hipError_t launch_sort_hist(Ctrl* ctrl, int buf, const uint32_t* R, const ulonglong2* Z, const ulonglong2* X,
-                            int with_x, uint32_t* hist, hipStream_t s, int grid) {
-    k_sort_hist<<<dim3(grid), dim3(kThreads), 0, s>>>(ctrl, buf, R, Z, X, with_x, hist);
+                            const SortPlan& plan, uint32_t* hist, hipStream_t s, int grid) {
+    k_sort_hist<<<dim3(grid), dim3(kThreads), 0, s>>>(ctrl, buf, R, Z, X, plan, hist);
     return hipGetLastError();
 }
 
@@ -957,10 +958,19 @@ hipError_t launch_group_sort(const GroupSortArgs& a, int dtype, int lp, hipStrea
     return hipGetLastError();
 }
 
-hipError_t launch_sort_pass(const SortPassArgs& a, int dtype, int lp, hipStream_t s, int grid) {
-#define L_SP(T, L) k_sort_pass<T, L><<<dim3(grid), dim3(kThreads), 0, s>>>(a)
-    ORQA_DISPATCH(dtype, lp, L_SP);
+hipError_t launch_sort_pass(const SortPassArgs& a, int ipt, int dtype, int lp, hipStream_t s, int grid) {
+    if (a.w < 1 || a.w > 8) return hipErrorInvalidValue;
+    if (ipt == 8) {
+#define L_SP(T, L) k_sort_pass<T, L, 8><<<dim3(grid), dim3(kThreads), 0, s>>>(a)
+        ORQA_DISPATCH(dtype, lp, L_SP);
 #undef L_SP
+    } else if (ipt == 16) {
+#define L_SP(T, L) k_sort_pass<T, L, 16><<<dim3(grid), dim3(kThreads), 0, s>>>(a)
+        ORQA_DISPATCH(dtype, lp, L_SP);
+#undef L_SP
+    } else {
+        return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
