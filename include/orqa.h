@@ -244,6 +244,8 @@ int pauli_sum_load_scorer(ps_handle* h, const ps_scorer* s);
  *                  in-group sort, and sorts of general gates);
  *                  sort_digit_bits, sort_items_per_thread the configuration
  *                  of the last one (pauli_sum_set_sort_config)
+ *   run_merges     general gates sorted by gathering their runs (parents;
+ *                  children by class) and merging them pairwise
  */
 typedef struct {
     double updates, gates;
@@ -254,6 +256,7 @@ typedef struct {
     double graph_replays, graph_captures;
     double score_launches, score_in, score_ms;
     double radix_sorts, sort_digit_bits, sort_items_per_thread;
+    double run_merges;
 } ps_stats;
 
 int pauli_sum_set_timing(ps_handle* h, int enable);

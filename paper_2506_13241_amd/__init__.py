@@ -48,7 +48,7 @@ class ps_stats(ctypes.Structure):
         "updates", "gates", "rx_launches", "rx_in", "rx_out", "rx_ms", "cliff_launches", "cliff_in", "cliff_ms",
         "sort_passes", "sort_elems", "sort_ms", "bytes_per_string", "graph_replays", "graph_captures",
         "score_launches", "score_in", "score_ms",
-        "radix_sorts", "sort_digit_bits", "sort_items_per_thread")]
+        "radix_sorts", "sort_digit_bits", "sort_items_per_thread", "run_merges")]
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_}

@@ -171,6 +171,12 @@ struct ps_handle {
     hipEvent_t sort_ev[2] = {nullptr, nullptr};
     int sort_last = 0;
     double radix_sorts = 0;
+    // general gates: runs of the last branch (-1: unsorted output, radix
+    // sort), the merge-path split buffer and the count of run merges
+    int gen_run_bits = -1;
+    uint64_t* msplit = nullptr;
+    size_t msplit_words = 0;
+    double run_merges = 0;
 };
 
 namespace {
@@ -554,6 +560,27 @@ int enqueue_gen_branch(ps_handle* h, int in, int out, int mx_in, double eps_in, 
     a.zj0 = st.gen.z[0];
     a.zj1 = st.gen.z[1];
     a.keep_rot = (st.gen.x[0] | st.gen.x[1]) == 0 ? 1 : 0;
+    // children form at most 2^b sorted runs (b = key bits the generator
+    // flips) when the output is written in the order the input is sorted in:
+    // x as stored (x_J = 0) or no stored rotation
+    h->gen_run_bits = -1;
+    const int b = __builtin_popcountll(st.gen.x[0]) + __builtin_popcountll(st.gen.x[1]) +
+                  __builtin_popcountll(st.gen.z[0]) + __builtin_popcountll(st.gen.z[1]);
+    if ((a.keep_rot || h->xrot == 0) && b <= kRunMaxBits) {
+        int q = 0;
+        for (int isz = 0; isz < 2; ++isz)
+            for (int bit = 0; bit < 128; ++bit) {
+                const uint64_t* m = isz ? st.gen.z : st.gen.x;
+                if ((m[bit >> 6] >> (bit & 63)) & 1u) {
+                    a.run_pos[q] = static_cast<uint8_t>(bit);
+                    a.run_isz[q] = static_cast<uint8_t>(isz);
+                    ++q;
+                }
+            }
+        a.run_bits = b;
+        a.Tout = h->rank[out];
+        h->gen_run_bits = b;
+    }
     size_t slot;
     int rc = ev_begin(h, 1, &slot);
     if (rc) return rc;
@@ -636,6 +663,118 @@ int run_rx_graph(ps_handle* h, const std::vector<GateTrig>& trigs, double pend0,
 
 // Re-sort buffer `b` (front only, with group ranks) by (rank, z).  Returns the
 // buffer holding the result in *result.
+// Sort of a general gate's branch output (buffer b) whose entries carry run
+// tags (0 parents, 1 + class children, at most 2^bits classes): one stable
+// radix pass on the tag gathers the runs, each sorted by (x, z); a tree of
+// pairwise merges then sorts the whole.  Result buffer in *result.
+int merge_gen_runs(ps_handle* h, int b, int bits, int* result) {
+    Ctrl c;
+    int rc = read_ctrl(h, &c);
+    if (rc) return rc;
+    const uint64_t n = c.nf[b];
+    *result = b;
+    if (c.err || n <= 1) return PS_OK;
+    const size_t need = n / kMergeTile + kMergeMaxPairs + 2;
+    if (need > h->msplit_words) {
+        if (h->msplit) HIP_TRY(hipFree(h->msplit));
+        h->msplit = nullptr;
+        h->msplit_words = 0;
+        const size_t words = need + need / 4;
+        if (hipMalloc(reinterpret_cast<void**>(&h->msplit), words * 8) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(PS_ERR_CAPACITY, "hipMalloc failed for %zu merge splits", words);
+        }
+        h->msplit_words = words;
+    }
+    SortPlan plan{};
+    plan.npass = 1;
+    plan.lo[0] = 128;  // the tag sits in the rank word of the key
+    plan.w[0] = static_cast<uint8_t>(bits + 1);
+    const int nrun = 1 + (1 << bits);
+    HIP_TRY(hipMemsetAsync(h->hist, 0, 256 * sizeof(uint32_t), h->stream));
+    HIP_TRY(launch_sort_hist(h->ctrl, b, h->rank[b], h->buf[b].Z, h->buf[b].X, plan, h->hist, h->stream, h->grid));
+    std::vector<uint32_t> cnt(256);
+    HIP_TRY(hipMemcpyAsync(cnt.data(), h->hist, 256 * sizeof(uint32_t), hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    std::vector<uint32_t> base(256, 0);
+    std::vector<std::pair<uint64_t, uint64_t>> segs;  // (start, length) of the non-empty runs
+    uint64_t run = 0;
+    for (int k = 0; k < 256; ++k) {
+        base[k] = static_cast<uint32_t>(run);
+        if (cnt[k] && k >= nrun) return fail(PS_ERR_DEVICE, "run tag %d out of range", k);
+        if (cnt[k]) segs.push_back({run, cnt[k]});
+        run += cnt[k];
+    }
+    if (run != n) return fail(PS_ERR_DEVICE, "run tags cover %llu of %llu entries", (unsigned long long)run,
+                              (unsigned long long)n);
+    if (segs.size() <= 1) return PS_OK;  // a single run: sorted already
+    HIP_TRY(hipMemcpyAsync(h->digit_base, base.data(), 256 * sizeof(uint32_t), hipMemcpyHostToDevice, h->stream));
+    SortPassArgs a{};
+    a.ctrl = h->ctrl;
+    a.n = n;
+    a.lo = 128;
+    a.w = bits + 1;
+    a.digit_base = h->digit_base;
+    a.Rs = h->rank[b];
+    a.Zs = h->buf[b].Z;
+    a.Xs = h->buf[b].X;
+    a.Cs = h->buf[b].C;
+    a.Rd = h->rank[1 - b];
+    a.Zd = h->buf[1 - b].Z;
+    a.Xd = h->buf[1 - b].X;
+    a.Cd = h->buf[1 - b].C;
+    a.status = h->status;
+    a.max_tiles = h->status_words / 256;
+    a.dst_buf = 1 - b;
+    size_t slot;
+    rc = ev_begin(h, 2, &slot);
+    if (rc) return rc;
+    HIP_TRY(launch_sort_pass(a, 8, h->dtype, h->LP, h->stream, h->grid));
+    rc = ev_end(h, slot);
+    if (rc) return rc;
+    h->sort_passes += 1;
+    h->sort_elems += double(n);
+    int src = 1 - b;
+    while (segs.size() > 1) {
+        MergeArgs m{};
+        m.ctrl = h->ctrl;
+        m.n = n;
+        m.dst_buf = 1 - src;
+        std::vector<std::pair<uint64_t, uint64_t>> next;
+        uint64_t tiles = 0;
+        for (size_t i = 0; i < segs.size(); i += 2) {
+            MergePair& P = m.pairs[m.npairs++];
+            P.a0 = segs[i].first;
+            P.na = segs[i].second;
+            P.nb = i + 1 < segs.size() ? segs[i + 1].second : 0;
+            P.tile0 = tiles;
+            tiles += (P.na + P.nb + kMergeTile - 1) / kMergeTile;
+            next.push_back({P.a0, P.na + P.nb});
+        }
+        m.ntiles = tiles;
+        m.Xs = h->buf[src].X;
+        m.Zs = h->buf[src].Z;
+        m.Cs = h->buf[src].C;
+        m.Xd = h->buf[1 - src].X;
+        m.Zd = h->buf[1 - src].Z;
+        m.Cd = h->buf[1 - src].C;
+        m.split = h->msplit;
+        rc = ev_begin(h, 2, &slot);
+        if (rc) return rc;
+        HIP_TRY(launch_merge_pairs(m, h->dtype, h->LP, h->stream));
+        rc = ev_end(h, slot);
+        if (rc) return rc;
+        h->sort_passes += 1;
+        h->sort_elems += double(n);
+        segs.swap(next);
+        src = 1 - src;
+    }
+    h->run_merges += 1;
+    *result = src;
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    return ev_collect(h);
+}
+
 // Radix-sort candidates: (digit bits, items per thread).  Narrower digits
 // give longer runs per bucket in each tile (better write coalescing) at the
 // price of more passes; larger tiles do the same for fewer look-back steps.
@@ -672,7 +811,7 @@ int pick_sort_candidate(const ps_handle* h, int kind, int cls, uint64_t n) {
 }
 
 int sort_by_rank_z(ps_handle* h, int b, int* result, bool full_key = false, bool try_groups = true,
-                   bool* overflowed = nullptr) {
+                   bool* overflowed = nullptr, int run_bits = -1) {
     if (overflowed) *overflowed = false;
     Ctrl c;
     int rc = read_ctrl(h, &c);
@@ -713,6 +852,7 @@ int sort_by_rank_z(ps_handle* h, int b, int* result, bool full_key = false, bool
         HIP_TRY(hipMemcpyAsync(&h->ctrl->aux[2], &zero, 8, hipMemcpyHostToDevice, h->stream));
         HIP_TRY(hipMemcpyAsync(&h->ctrl->nf[1 - b], &zero, 8, hipMemcpyHostToDevice, h->stream));
     }
+    if (full_key && run_bits >= 0) return merge_gen_runs(h, b, run_bits, result);
     const int kind = full_key ? 1 : 0;
     int cls = 0;
     while (cls < 63 && (uint64_t(2) << cls) <= n) ++cls;
@@ -972,6 +1112,7 @@ int pauli_sum_destroy(ps_handle* h) {
     for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
     for (hipEvent_t e : h->sort_ev)
         if (e) (void)hipEventDestroy(e);
+    if (h->msplit) (void)hipFree(h->msplit);
     if (h->has_scorer) scorer_free(&h->scorer);
     drop_graphs(h);
     if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
@@ -1247,7 +1388,7 @@ int apply_rotation_layer(ps_handle* h, const ps_pauli* gens, const double* theta
             const bool try_groups = gen_zonly && h->gs_skip == 0;
             if (gen_zonly && h->gs_skip > 0) --h->gs_skip;
             bool over = false;
-            rc = sort_by_rank_z(h, h->cur, &res, true, try_groups, &over);
+            rc = sort_by_rank_z(h, h->cur, &res, true, try_groups, &over, h->gen_run_bits);
             if (over) h->gs_skip = 32;
             if (rc) return rc;
             rc = enqueue_gen_reduce(h, res, 1 - res, 1 - mx_branch);
@@ -1433,10 +1574,11 @@ int pauli_sum_stats(ps_handle* h, ps_stats* out, int reset) {
     out->score_launches = double(c.aux[1]);
     out->score_ms = h->ms[3];
     out->radix_sorts = h->radix_sorts;
+    out->run_merges = h->run_merges;
     out->sort_digit_bits = kSortCandBits[h->sort_last];
     out->sort_items_per_thread = kSortCandIpt[h->sort_last];
     if (reset) {
-        h->radix_sorts = 0;
+        h->radix_sorts = h->run_merges = 0;
         h->graph_replays = h->graph_captures = 0;
         h->ms[3] = 0;
         const uint64_t z2[2] = {0, 0};

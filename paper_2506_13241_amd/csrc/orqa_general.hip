@@ -22,6 +22,20 @@ __device__ __forceinline__ bool gen_child_negative(const ulonglong2& xp, const u
     return (e & 3) == 1;
 }
 
+// Run of a child: the parent's bits at the generator's key positions.  Parents
+// of one class keep their relative order under the xor with J (the first bit
+// where two of them differ is not one that J flips), so the children of one
+// class, in input order, form a sorted run.
+__device__ __forceinline__ uint32_t run_class(const GenArgs& A, const ulonglong2& x, const ulonglong2& z) {
+    uint32_t c = 0;
+    for (int q = 0; q < A.run_bits; ++q) {
+        const ulonglong2& v = A.run_isz[q] ? z : x;
+        const int pos = A.run_pos[q];
+        c |= uint32_t(((pos < 64 ? v.x : v.y) >> (pos & 63)) & 1u) << q;
+    }
+    return c;
+}
+
 template <typename CT, int LP>
 __device__ __forceinline__ bool gen_keep(const CT* c, const double* thr) {
     bool keep = false;
@@ -113,6 +127,7 @@ __global__ __launch_bounds__(kThreads) void k_gen_branch(GenArgs A, GateTrig g) 
                     A.Zout[o] = zs[k];
 #pragma unroll
                     for (int a = 0; a < LP; ++a) Cout[o * LP + a] = ce[a];
+                    if (A.Tout) A.Tout[o] = 0u;
                 }
                 ++o;
                 continue;
@@ -123,6 +138,7 @@ __global__ __launch_bounds__(kThreads) void k_gen_branch(GenArgs A, GateTrig g) 
                     A.Zout[o] = zs[k];
 #pragma unroll
                     for (int a = 0; a < LP; ++a) Cout[o * LP + a] = Arith<CT>::scale_c(g, a, ce[a]);
+                    if (A.Tout) A.Tout[o] = 0u;
                 }
                 ++o;
             }
@@ -135,6 +151,7 @@ __global__ __launch_bounds__(kThreads) void k_gen_branch(GenArgs A, GateTrig g) 
                     A.Zout[o] = zc;
 #pragma unroll
                     for (int a = 0; a < LP; ++a) Cout[o * LP + a] = Arith<CT>::scale_s(g, a, ce[a], neg);
+                    if (A.Tout) A.Tout[o] = 1u + run_class(A, xw, zs[k]);
                 }
                 ++o;
             }
@@ -237,6 +254,104 @@ __global__ __launch_bounds__(kThreads) void k_gen_reduce(GenArgs A) {
             ctrl->nb[A.out_buf] = 0;
         }
     }
+}
+
+// ================================================================ merge of sorted runs
+// (x, z) order, x major, as the radix sort produces it.
+__device__ __forceinline__ bool key_le(const ulonglong2& xa, const ulonglong2& za, const ulonglong2& xb,
+                                       const ulonglong2& zb) {
+    return k_eq(xa, xb) ? k_le(za, zb) : k_lt(xa, xb);
+}
+
+__device__ __forceinline__ int merge_pair_of(const MergeArgs& A, uint64_t tile) {
+    int p = 0;
+    while (p + 1 < A.npairs && A.pairs[p + 1].tile0 <= tile) ++p;
+    return p;
+}
+
+// Merge path: the number of A elements among the first d outputs of the
+// merge of A and B, A first on equal keys.
+__global__ __launch_bounds__(kThreads) void k_merge_split(MergeArgs A) {
+    const uint64_t t = blockIdx.x * uint64_t(kThreads) + threadIdx.x;
+    if (t == 0) {
+        A.ctrl->nf[A.dst_buf] = A.n;
+        A.ctrl->nb[A.dst_buf] = 0;
+    }
+    if (t >= A.ntiles) return;
+    const MergePair P = A.pairs[merge_pair_of(A, t)];
+    const uint64_t d = (t - P.tile0) * kMergeTile;
+    const uint64_t b0 = P.a0 + P.na;
+    uint64_t lo = d > P.nb ? d - P.nb : 0, hi = d < P.na ? d : P.na;
+    while (lo < hi) {
+        const uint64_t mid = (lo + hi) >> 1;
+        const uint64_t j = b0 + d - 1 - mid;
+        if (key_le(A.Xs[P.a0 + mid], A.Zs[P.a0 + mid], A.Xs[j], A.Zs[j])) lo = mid + 1;
+        else hi = mid;
+    }
+    A.split[t] = lo;
+}
+
+// One output tile per workgroup: its A and B ranges staged in LDS, each thread
+// merges kMergeIPT consecutive outputs from its own merge-path split.
+template <typename CT, int LP>
+__global__ __launch_bounds__(kThreads) void k_merge_pairs(MergeArgs A) {
+    __shared__ ulonglong2 sX[kMergeTile];
+    __shared__ ulonglong2 sZ[kMergeTile];
+    const uint64_t t = blockIdx.x;
+    const MergePair P = A.pairs[merge_pair_of(A, t)];
+    const uint64_t total = P.na + P.nb;
+    const uint64_t d0 = (t - P.tile0) * kMergeTile;
+    const uint64_t d1 = d0 + kMergeTile < total ? d0 + kMergeTile : total;
+    const uint64_t a_lo = A.split[t];
+    const uint64_t a_hi = d1 == total ? P.na : A.split[t + 1];
+    const uint64_t b_lo = d0 - a_lo;
+    const int cntA = int(a_hi - a_lo), cnt = int(d1 - d0), cntB = cnt - cntA;
+    const uint64_t gA = P.a0 + a_lo, gB = P.a0 + P.na + b_lo;
+    for (int i = threadIdx.x; i < cnt; i += kThreads) {
+        const uint64_t g = i < cntA ? gA + i : gB + (i - cntA);
+        sX[i] = A.Xs[g];
+        sZ[i] = A.Zs[g];
+    }
+    __syncthreads();
+    const int dd = threadIdx.x * kMergeIPT;
+    if (dd >= cnt) return;
+    int lo = dd > cntB ? dd - cntB : 0, hi = dd < cntA ? dd : cntA;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        const int j = cntA + dd - 1 - mid;
+        if (key_le(sX[mid], sZ[mid], sX[j], sZ[j])) lo = mid + 1;
+        else hi = mid;
+    }
+    int ai = lo, bi = dd - lo;
+    const CT* __restrict__ Cs = static_cast<const CT*>(A.Cs);
+    CT* __restrict__ Cd = static_cast<CT*>(A.Cd);
+#pragma unroll
+    for (int k = 0; k < kMergeIPT; ++k) {
+        const int oo = dd + k;
+        if (oo >= cnt) break;
+        const bool takeA = ai < cntA && (bi >= cntB || key_le(sX[ai], sZ[ai], sX[cntA + bi], sZ[cntA + bi]));
+        const int l = takeA ? ai : cntA + bi;
+        const uint64_t src = takeA ? gA + ai : gB + bi;
+        const uint64_t out = P.a0 + d0 + oo;
+        A.Xd[out] = sX[l];
+        A.Zd[out] = sZ[l];
+#pragma unroll
+        for (int a = 0; a < LP; ++a) Cd[out * LP + a] = Cs[src * LP + a];
+        if (takeA) ++ai;
+        else ++bi;
+    }
+}
+
+hipError_t launch_merge_pairs(const MergeArgs& a, int dtype, int lp, hipStream_t s) {
+    if (a.npairs < 1 || a.npairs > kMergeMaxPairs || a.ntiles == 0) return hipErrorInvalidValue;
+    const unsigned sgrid = unsigned((a.ntiles + kThreads - 1) / kThreads);
+    k_merge_split<<<dim3(sgrid), dim3(kThreads), 0, s>>>(a);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+#define L_MP(T, L) k_merge_pairs<T, L><<<dim3(unsigned(a.ntiles)), dim3(kThreads), 0, s>>>(a)
+    ORQA_DISPATCH(dtype, lp, L_MP);
+#undef L_MP
+    return hipGetLastError();
 }
 
 hipError_t launch_gen_branch(const GenArgs& a, const GateTrig& g, int dtype, int lp, hipStream_t s, int grid) {

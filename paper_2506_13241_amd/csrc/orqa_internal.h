@@ -199,7 +199,39 @@ struct GenArgs {
     int xrot, nq;
     uint64_t xj0, xj1, zj0, zj1;  // the generator sigma_J
     int keep_rot;                  // x_J = 0: write x as stored (rotated), keep the x-group order
+    // run tags (NULL: none): 0 for a parent, 1 + class for a child, the class
+    // being the parent's bits at the generator's run_bits key positions
+    // (run_pos, in z when run_isz, else in x as written)
+    uint32_t* Tout;
+    int run_bits;
+    uint8_t run_pos[4];
+    uint8_t run_isz[4];
 };
+constexpr int kRunMaxBits = 4;  // at most 1 + 2^4 sorted runs per general gate
+
+// Merge of pairs of adjacent sorted runs (general gates): pair p merges
+// [a0, a0 + na) and [a0 + na, a0 + na + nb) of the source into [a0, ...) of
+// the destination; its output tiles are tile0 .. tile0 + ceil((na+nb)/T) - 1.
+constexpr int kMergeIPT = 4;
+constexpr int kMergeTile = kThreads * kMergeIPT;  // 1024
+constexpr int kMergeMaxPairs = 16;
+struct MergePair {
+    uint64_t a0, na, nb, tile0;
+};
+struct MergeArgs {
+    Ctrl* ctrl;
+    int npairs, dst_buf;
+    uint64_t ntiles, n;
+    MergePair pairs[kMergeMaxPairs];
+    const ulonglong2* Xs;
+    const ulonglong2* Zs;
+    const void* Cs;
+    ulonglong2* Xd;
+    ulonglong2* Zd;
+    void* Cd;
+    uint64_t* split;  // per tile: A elements before its first output (within its pair)
+};
+hipError_t launch_merge_pairs(const MergeArgs& a, int dtype, int lp, hipStream_t s);
 hipError_t launch_gen_branch(const GenArgs& a, const GateTrig& g, int dtype, int lp, hipStream_t s, int grid);
 hipError_t launch_gen_reduce(const GenArgs& a, int dtype, int lp, hipStream_t s, int grid);
 

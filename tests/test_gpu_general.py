@@ -143,7 +143,8 @@ def test_z_only_rotation_inside_an_rx_run_keeps_the_stream():
     """A non-Clifford RZZ between RX gates: the general path keeps the stored x
     rotation (children stay in their x-group), sorts inside the groups, and
     the RX run continues on its streaming path; against the oracle, and a
-    large x-group forces the radix-sort fallback of the same stage."""
+    large x-group forces the fallback of the same stage (gathering the runs
+    and merging them)."""
     n = 14
     terms, coeffs = w.random_pauli_set(n, 3000, seed=51)
     def rot(ops, th):
@@ -163,4 +164,27 @@ def test_z_only_rotation_inside_an_rx_run_keeps_the_stream():
         g.apply_rotation_layer(gl, 1e-6)
         o.apply(gl, 1e-6)
         say(f"{label}: |O| = {g.size()}")
+        assert_same_operator(g, o, coeff_exact=True)
+
+
+def test_run_merge_sorts_general_gates_with_few_flipped_bits():
+    """Generators flipping b <= 4 key bits (X and Z letters count one, Y two)
+    sort their branch output by gathering 1 + 2^b sorted runs and merging them
+    pairwise (odd run counts, several merge tiles); b = 5 takes the radix
+    sort.  Bit for bit against the oracle after every gate."""
+    n = 14
+    terms, coeffs = w.random_pauli_set(n, 80000, seed=81)
+    specs = [({3: "Z", 6: "X"}, 0.7, 2), ({1: "Y", 7: "Y"}, 0.45, 4), ({2: "X", 9: "Z", 11: "Z"}, 1.1, 3),
+             ({5: "Y"}, 0.3, 2), ({0: "X", 4: "X", 8: "X", 12: "Z"}, 0.6, 4), ({1: "Y", 2: "Y", 3: "Z"}, 0.8, 5)]
+    g, o = _both(n, terms, coeffs)
+    for ops, th, b in specs:
+        gate = w.GateList(w.pauli_words(n, ops)[None, :], np.array([[th]]))
+        before = g.stats()
+        g.apply_rotation_layer(gate, 1e-7)
+        o.apply(gate, 1e-7)
+        after = g.stats()
+        merged = after["run_merges"] - before["run_merges"]
+        radix = after["radix_sorts"] - before["radix_sorts"]
+        say(f"{ops} (b = {b}): |O| = {g.size()}, run merges {merged:.0f}, radix sorts {radix:.0f}")
+        assert (merged, radix) == ((1, 0) if b <= 4 else (0, 1))
         assert_same_operator(g, o, coeff_exact=True)

@@ -38,11 +38,13 @@ def _resort_case():
 
 
 def _general_case():
-    """Rotations of weight <= 3 with X/Y letters on a 14-qubit register,
-    80k strings: every gate takes the (x, z) radix sort."""
+    """Four rotations on a 14-qubit register, 80k strings, each generator
+    flipping five or more key bits (a Y letter flips two), so every gate takes
+    the (x, z) radix sort rather than the merge of its runs."""
     n = 14
     terms, coeffs = w.random_pauli_set(n, 80000, seed=71)
-    gates = w.random_gates(n, 4, seed=72, max_weight=3)
+    gens = [{1: "Y", 4: "Y", 9: "X"}, {0: "Y", 2: "X", 5: "Y"}, {3: "Y", 7: "Y", 8: "Y"}, {2: "Z", 6: "Y", 10: "Y"}]
+    gates = w.GateList(np.stack([w.pauli_words(n, ops) for ops in gens]), np.array([[0.3], [0.7], [1.1], [0.5]]))
     return n, gates, terms, coeffs
 
 
@@ -64,6 +66,7 @@ def test_every_configuration_matches_the_oracle(bits, ipt):
     g.apply_rotation_layer(gates, 1e-6)
     o.apply(gates, 1e-6)
     say(f"({bits}, {ipt}): |O| = {g.size()}, sorts {g.stats()['radix_sorts']}")
+    assert g.stats()["radix_sorts"] == 4
     assert_same_operator(g, o, coeff_exact=True)
 
 
@@ -99,7 +102,7 @@ def test_tuner_explores_all_candidates():
     import paper_2506_13241_amd as P
     n = 16
     terms, coeffs = w.random_pauli_set(n, 150000, seed=73)
-    gate = w.GateList(w.pauli_words(n, {3: "Y", 9: "X"})[None, :], np.array([[0.4]]))
+    gate = w.GateList(w.pauli_words(n, {3: "Y", 9: "X", 12: "Y"})[None, :], np.array([[0.4]]))
     g = gpu_sum(n, terms, coeffs)
     o = OracleSum(n, terms, coeffs)
     used, sizes = [], []
