@@ -220,6 +220,8 @@ def main():
         "ms_clifford_total": round(st["cliff_ms"], 3),
         "ms_sort_total": round(st["sort_ms"], 3),
         "sort_passes": int(st["sort_passes"]),
+        "radix_sorts": int(st["radix_sorts"]),
+        "run_merges": int(st["run_merges"]),
         "paper_time_per_gate_ms": round(dt / args.steps / 271 * 1e3, 4),
     }
     if st["score_launches"] > 0:
