@@ -44,11 +44,31 @@ __device__ __forceinline__ bool gen_keep(const CT* c, const double* thr) {
     return keep;
 }
 
+// Element k of thread tid in a tile is input t0 + k * 256 + tid (striped, so
+// loads and stores of a wave cover contiguous memory).  Its output offset in
+// input order: the outputs of every element with a smaller k, then those of
+// threads before tid at the same k.  Counts per element are at most 2, so the
+// four per-k scans fit in two packed 16-bit scans.
+static_assert(kGenIPT == 4, "scan_striped4 packs four counts");
+__device__ __forceinline__ void scan_striped4(const uint32_t (&c)[4], uint32_t* s_wave, uint32_t (&off)[4],
+                                              uint32_t& total) {
+    uint32_t t01, t23;
+    const uint32_t o01 = block_excl_scan(c[0] | (c[1] << 16), s_wave, t01);
+    const uint32_t o23 = block_excl_scan(c[2] | (c[3] << 16), s_wave, t23);
+    const uint32_t T0 = t01 & 0xFFFFu, T1 = t01 >> 16, T2 = t23 & 0xFFFFu, T3 = t23 >> 16;
+    off[0] = o01 & 0xFFFFu;
+    off[1] = T0 + (o01 >> 16);
+    off[2] = T0 + T1 + (o23 & 0xFFFFu);
+    off[3] = T0 + T1 + T2 + (o23 >> 16);
+    total = T0 + T1 + T2 + T3;
+}
+
 // Branch: reads the (virtual, x-rotated) input, applies the pending truncation,
 // writes parents and children compacted to the front of the output, in input
-// order, in true x (or, when x_J = 0, with x as stored: then every output
-// stays in its parent's x-group and the groups keep their order).  Output
-// offsets by a two-level decoupled look-back over tiles.
+// order (each parent before its child), in true x (or, when x_J = 0, with x
+// as stored: then every output stays in its parent's x-group and the groups
+// keep their order).  Output offsets by a two-level decoupled look-back over
+// tiles.
 template <typename CT, int LP>
 __global__ __launch_bounds__(kThreads) void k_gen_branch(GenArgs A, GateTrig g) {
     __shared__ uint32_t sWave[4];
@@ -75,10 +95,9 @@ __global__ __launch_bounds__(kThreads) void k_gen_branch(GenArgs A, GateTrig g) 
         const uint64_t t0 = uint64_t(tile) * kGenTile;
         ulonglong2 xs[kGenIPT], zs[kGenIPT];
         uint32_t nout[kGenIPT];
-        uint32_t cnt = 0;
 #pragma unroll
         for (int k = 0; k < kGenIPT; ++k) {
-            const uint64_t i = t0 + uint64_t(tid) * kGenIPT + k;  // blocked: outputs keep the input order
+            const uint64_t i = t0 + uint64_t(k) * kThreads + tid;
             nout[k] = 0;
             xs[k] = make_ulonglong2(0, 0);
             zs[k] = make_ulonglong2(0, 0);
@@ -90,10 +109,9 @@ __global__ __launch_bounds__(kThreads) void k_gen_branch(GenArgs A, GateTrig g) 
             const ulonglong2 xt = rotl_n(xs[k], A.xrot, A.nq);
             const bool anti = ((k_popc_and(xt, zj) + k_popc_and(zs[k], xj)) & 1) != 0;
             nout[k] = anti ? uint32_t(g.any_c != 0) + uint32_t(g.any_s != 0) : 1u;
-            cnt += nout[k];
         }
-        uint32_t tot;
-        const uint32_t off = block_excl_scan(cnt, sWave, tot);
+        uint32_t tot, off[kGenIPT];
+        scan_striped4(nout, sWave, off, tot);
         if (wave == 0) {
             const uint64_t gmax = A.max_tiles / 64 + 2;
             const uint64_t b = lookback_wave2(A.status, A.status + 2 * A.max_tiles, tile, ep, tot, &ctrl->err);
@@ -112,11 +130,11 @@ __global__ __launch_bounds__(kThreads) void k_gen_branch(GenArgs A, GateTrig g) 
                 ctrl->nb[A.out_buf] = 0;
             }
         }
-        uint64_t o = base + off;
 #pragma unroll
         for (int k = 0; k < kGenIPT; ++k) {
             if (nout[k] == 0) continue;
-            const uint64_t i = t0 + uint64_t(tid) * kGenIPT + k;
+            uint64_t o = base + off[k];
+            const uint64_t i = t0 + uint64_t(k) * kThreads + tid;
             const CT* ce = Cin + vphys(i, nf, A.cap) * LP;
             const ulonglong2 xt = rotl_n(xs[k], A.xrot, A.nq);
             const ulonglong2 xw = A.keep_rot ? xs[k] : xt;  // x as written
@@ -195,22 +213,20 @@ __global__ __launch_bounds__(kThreads) void k_gen_reduce(GenArgs A) {
         const uint32_t tile = acquire_tile(ctrl, &sTile);
         if (tile >= ntiles) break;
         const uint64_t t0 = uint64_t(tile) * kGenTile;
-        // thread owns consecutive positions (blocked), so the scan keeps key order
-        const uint64_t i0 = t0 + uint64_t(tid) * kGenIPT;
-        uint32_t first = 0, cnt = 0;
+        uint32_t first[kGenIPT];
 #pragma unroll
         for (int k = 0; k < kGenIPT; ++k) {
-            const uint64_t i = i0 + k;
+            const uint64_t i = t0 + uint64_t(k) * kThreads + tid;  // striped, scanned in input order
+            first[k] = 0;
             if (i >= n) continue;
             const ulonglong2 x = A.Xin[i], z = A.Zin[i];
             const bool f = i == 0 || !k_eq(x, A.Xin[i - 1]) || !k_eq(z, A.Zin[i - 1]);
             if (f && i + 2 < n && k_eq(x, A.Xin[i + 2]) && k_eq(z, A.Zin[i + 2]))
                 atomicOr(&ctrl->err, kErrInternal);  // three entries of one key cannot occur
-            first |= uint32_t(f) << k;
-            cnt += f;
+            first[k] = f;
         }
-        uint32_t tot;
-        const uint32_t off = block_excl_scan(cnt, sWave, tot);
+        uint32_t tot, off[kGenIPT];
+        scan_striped4(first, sWave, off, tot);
         if (wave == 0) {
             const uint64_t b = lookback_wave2(A.status, A.status + 2 * A.max_tiles, tile, ep, tot, &ctrl->err);
             if (lane_id() == 0) sBase = b;
@@ -221,11 +237,11 @@ __global__ __launch_bounds__(kThreads) void k_gen_reduce(GenArgs A) {
             ctrl->nf[A.out_buf] = base + tot;
             ctrl->nb[A.out_buf] = 0;
         }
-        uint64_t o = base + off;
 #pragma unroll
         for (int k = 0; k < kGenIPT; ++k) {
-            if (!((first >> k) & 1u)) continue;
-            const uint64_t i = i0 + k;
+            if (!first[k]) continue;
+            const uint64_t o = base + off[k];
+            const uint64_t i = t0 + uint64_t(k) * kThreads + tid;
             const ulonglong2 x = A.Xin[i], z = A.Zin[i];
             const bool two = i + 1 < n && k_eq(x, A.Xin[i + 1]) && k_eq(z, A.Zin[i + 1]);
             A.Xout[o] = x;
@@ -237,7 +253,6 @@ __global__ __launch_bounds__(kThreads) void k_gen_reduce(GenArgs A) {
                 Cout[o * LP + a] = v;
                 vmax[a] = fmax(vmax[a], absd(v));
             }
-            ++o;
         }
         __syncthreads();
     }
@@ -292,11 +307,13 @@ __global__ __launch_bounds__(kThreads) void k_merge_split(MergeArgs A) {
 }
 
 // One output tile per workgroup: its A and B ranges staged in LDS, each thread
-// merges kMergeIPT consecutive outputs from its own merge-path split.
+// finds the sources of kMergeIPT consecutive outputs from its own merge-path
+// split, and the tile is then written in striped order (coalesced stores).
 template <typename CT, int LP>
 __global__ __launch_bounds__(kThreads) void k_merge_pairs(MergeArgs A) {
     __shared__ ulonglong2 sX[kMergeTile];
     __shared__ ulonglong2 sZ[kMergeTile];
+    __shared__ uint16_t sSrc[kMergeTile];
     const uint64_t t = blockIdx.x;
     const MergePair P = A.pairs[merge_pair_of(A, t)];
     const uint64_t total = P.na + P.nb;
@@ -314,31 +331,36 @@ __global__ __launch_bounds__(kThreads) void k_merge_pairs(MergeArgs A) {
     }
     __syncthreads();
     const int dd = threadIdx.x * kMergeIPT;
-    if (dd >= cnt) return;
-    int lo = dd > cntB ? dd - cntB : 0, hi = dd < cntA ? dd : cntA;
-    while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        const int j = cntA + dd - 1 - mid;
-        if (key_le(sX[mid], sZ[mid], sX[j], sZ[j])) lo = mid + 1;
-        else hi = mid;
+    if (dd < cnt) {
+        int lo = dd > cntB ? dd - cntB : 0, hi = dd < cntA ? dd : cntA;
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            const int j = cntA + dd - 1 - mid;
+            if (key_le(sX[mid], sZ[mid], sX[j], sZ[j])) lo = mid + 1;
+            else hi = mid;
+        }
+        int ai = lo, bi = dd - lo;
+#pragma unroll
+        for (int k = 0; k < kMergeIPT; ++k) {
+            const int oo = dd + k;
+            if (oo >= cnt) break;
+            const bool takeA = ai < cntA && (bi >= cntB || key_le(sX[ai], sZ[ai], sX[cntA + bi], sZ[cntA + bi]));
+            sSrc[oo] = uint16_t(takeA ? ai : cntA + bi);
+            if (takeA) ++ai;
+            else ++bi;
+        }
     }
-    int ai = lo, bi = dd - lo;
+    __syncthreads();
     const CT* __restrict__ Cs = static_cast<const CT*>(A.Cs);
     CT* __restrict__ Cd = static_cast<CT*>(A.Cd);
-#pragma unroll
-    for (int k = 0; k < kMergeIPT; ++k) {
-        const int oo = dd + k;
-        if (oo >= cnt) break;
-        const bool takeA = ai < cntA && (bi >= cntB || key_le(sX[ai], sZ[ai], sX[cntA + bi], sZ[cntA + bi]));
-        const int l = takeA ? ai : cntA + bi;
-        const uint64_t src = takeA ? gA + ai : gB + bi;
+    for (int oo = threadIdx.x; oo < cnt; oo += kThreads) {
+        const int l = sSrc[oo];
+        const uint64_t src = l < cntA ? gA + l : gB + (l - cntA);
         const uint64_t out = P.a0 + d0 + oo;
         A.Xd[out] = sX[l];
         A.Zd[out] = sZ[l];
 #pragma unroll
         for (int a = 0; a < LP; ++a) Cd[out * LP + a] = Cs[src * LP + a];
-        if (takeA) ++ai;
-        else ++bi;
     }
 }
 

@@ -647,12 +647,13 @@ __global__ __launch_bounds__(kThreads) void k_sort_hist(const Ctrl* __restrict__
     __shared__ uint32_t sh[kSortMaxPasses][256];
     const int np = plan.npass;
     const bool need_x = np > 0 && plan.lo[np - 1] + plan.w[np - 1] > 192;  // passes ascend in lo
+    const bool need_z = np > 0 && plan.lo[0] < 128;
     for (int i = threadIdx.x; i < np * 256; i += kThreads) (&sh[0][0])[i] = 0;
     __syncthreads();
     const uint64_t n = ctrl->nf[buf];
     if (!ctrl->err) {
         for (uint64_t i = blockIdx.x * uint64_t(kThreads) + threadIdx.x; i < n; i += uint64_t(gridDim.x) * kThreads) {
-            const ulonglong2 z = Z[i];
+            const ulonglong2 z = need_z ? Z[i] : ulonglong2{0, 0};
             const ulonglong2 x = need_x ? X[i] : ulonglong2{0, 0};
             const uint32_t r = R ? R[i] : 0u;
             for (int p = 0; p < np; ++p) atomicAdd(&sh[p][key_digit(plan.lo[p], plan.w[p], r, z, x)], 1u);
