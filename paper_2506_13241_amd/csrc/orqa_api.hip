@@ -549,8 +549,10 @@ GenArgs gen_args(ps_handle* h, int in, int out, int mx_in, int mx_out) {
     return a;
 }
 
-// General gate, first half: parents and children of every string, unsorted,
-// in true x (the stored rotation is undone).
+// General gate, first half: parents and children of every string, in input
+// order, in true x (the stored rotation is undone) unless x_J = 0 (then x as
+// stored); tagged by sorted run when the generator flips at most four key
+// bits and the output keeps the input's order.
 int enqueue_gen_branch(ps_handle* h, int in, int out, int mx_in, double eps_in, const Stage& st) {
     GenArgs a = gen_args(h, in, out, mx_in, 1 - mx_in);
     a.eps_in = eps_in;

@@ -188,3 +188,35 @@ def test_run_merge_sorts_general_gates_with_few_flipped_bits():
         say(f"{ops} (b = {b}): |O| = {g.size()}, run merges {merged:.0f}, radix sorts {radix:.0f}")
         assert (merged, radix) == ((1, 0) if b <= 4 else (0, 1))
         assert_same_operator(g, o, coeff_exact=True)
+
+
+def test_run_merge_after_capacity_growth_and_with_lanes():
+    """The tagged branch re-run after the handle grows (the run tags live in
+    per-capacity arrays that move with the growth), and run merges with
+    several lanes in binary64 and binary32."""
+    n = 16
+    terms, coeffs = w.random_pauli_set(n, 40000, seed=91)
+    gate = w.GateList(w.pauli_words(n, {0: "Y", 5: "X", 9: "Z"})[None, :], np.array([[0.77]]))
+    g = gpu_sum(n, terms, coeffs, capacity=45000)
+    o = OracleSum(n, terms, coeffs)
+    g.apply_rotation_layer(gate)
+    o.apply(gate)
+    assert g.stats()["run_merges"] == 1
+    assert_same_operator(g, o, coeff_exact=True)
+    terms, coeffs = w.random_pauli_set(n, 30000, seed=92, lanes=5)
+    gens = [{1: "Z", 2: "X"}, {3: "Y", 7: "Z"}, {4: "X", 6: "X", 8: "Z"}]
+    gl = w.GateList(np.stack([w.pauli_words(n, ops) for ops in gens]),
+                    np.random.default_rng(93).uniform(-1.5, 1.5, (3, 5)))
+    g64, o = gpu_sum(n, terms, coeffs), OracleSum(n, terms, coeffs)
+    g64.apply_rotation_layer(gl, 1e-6)
+    o.apply(gl, 1e-6)
+    assert g64.stats()["run_merges"] == 3
+    assert_same_operator(g64, o, coeff_exact=True)
+    g32 = gpu_sum(n, terms, coeffs, dtype=1)
+    g32.apply_rotation_layer(gl)
+    g64 = gpu_sum(n, terms, coeffs)
+    g64.apply_rotation_layer(gl)
+    k32, c32 = g32.export()
+    k64, c64 = g64.export()
+    assert np.array_equal(k32, k64)
+    assert np.abs(c32.astype(np.float64) - c64).max() <= 1e-5 * np.abs(c64).max()
