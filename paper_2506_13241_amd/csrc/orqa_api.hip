@@ -551,8 +551,8 @@ GenArgs gen_args(ps_handle* h, int in, int out, int mx_in, int mx_out) {
 
 // General gate, first half: parents and children of every string, in input
 // order, in true x (the stored rotation is undone) unless x_J = 0 (then x as
-// stored); tagged by sorted run when the generator flips at most four key
-// bits and the output keeps the input's order.
+// stored); tagged by sorted run when the generator flips few key bits and the
+// output keeps the input's order.
 int enqueue_gen_branch(ps_handle* h, int in, int out, int mx_in, double eps_in, const Stage& st) {
     GenArgs a = gen_args(h, in, out, mx_in, 1 - mx_in);
     a.eps_in = eps_in;
@@ -568,7 +568,11 @@ int enqueue_gen_branch(ps_handle* h, int in, int out, int mx_in, double eps_in, 
     h->gen_run_bits = -1;
     const int b = __builtin_popcountll(st.gen.x[0]) + __builtin_popcountll(st.gen.x[1]) +
                   __builtin_popcountll(st.gen.z[0]) + __builtin_popcountll(st.gen.z[1]);
-    if ((a.keep_rot || h->xrot == 0) && b <= kRunMaxBits) {
+    // passes: the run gather plus ceil(log2(1 + 2^b)) merge levels, against
+    // the radix sort's byte digits of x and z (fewer on small registers)
+    const int merge_passes = 1 + (b + 1);
+    const int radix_passes = 2 * ((h->nq + 7) / 8);
+    if ((a.keep_rot || h->xrot == 0) && b <= kRunMaxBits && (b <= 4 || merge_passes < radix_passes)) {
         int q = 0;
         for (int isz = 0; isz < 2; ++isz)
             for (int bit = 0; bit < 128; ++bit) {

@@ -204,17 +204,17 @@ struct GenArgs {
     // (run_pos, in z when run_isz, else in x as written)
     uint32_t* Tout;
     int run_bits;
-    uint8_t run_pos[4];
-    uint8_t run_isz[4];
+    uint8_t run_pos[6];
+    uint8_t run_isz[6];
 };
-constexpr int kRunMaxBits = 4;  // at most 1 + 2^4 sorted runs per general gate
+constexpr int kRunMaxBits = 6;  // at most 1 + 2^6 sorted runs per general gate
 
 // Merge of pairs of adjacent sorted runs (general gates): pair p merges
 // [a0, a0 + na) and [a0 + na, a0 + na + nb) of the source into [a0, ...) of
 // the destination; its output tiles are tile0 .. tile0 + ceil((na+nb)/T) - 1.
 constexpr int kMergeIPT = 4;
 constexpr int kMergeTile = kThreads * kMergeIPT;  // 1024
-constexpr int kMergeMaxPairs = 16;
+constexpr int kMergeMaxPairs = 64;
 struct MergePair {
     uint64_t a0, na, nb, tile0;
 };

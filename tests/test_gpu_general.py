@@ -220,3 +220,26 @@ def test_run_merge_after_capacity_growth_and_with_lanes():
     k64, c64 = g64.export()
     assert np.array_equal(k32, k64)
     assert np.abs(c32.astype(np.float64) - c64).max() <= 1e-5 * np.abs(c64).max()
+
+
+def test_run_merge_up_to_65_runs_on_127_qubits():
+    """On the 127-q register the radix sort needs 32 byte passes, so
+    generators flipping five or six key bits (33 and 65 runs, 7 and 8
+    passes) also take the run merge; seven bits take the radix sort."""
+    n = 127
+    lat = w.eagle_127()
+    terms, coeffs = w.random_pauli_set(n, 50000, seed=95, support=w.ball(lat, 62, 4))
+    specs = [({60: "Y", 61: "Y", 62: "X"}, 0.4, 5), ({55: "Y", 62: "Y", 70: "Y"}, 0.9, 6),
+             ({60: "Y", 61: "Y", 62: "Y", 63: "X"}, 0.6, 7)]
+    g, o = _both(n, terms, coeffs)
+    for ops, th, b in specs:
+        gate = w.GateList(w.pauli_words(n, ops)[None, :], np.array([[th]]))
+        before = g.stats()
+        g.apply_rotation_layer(gate, 1e-6)
+        o.apply(gate, 1e-6)
+        after = g.stats()
+        merged = after["run_merges"] - before["run_merges"]
+        radix = after["radix_sorts"] - before["radix_sorts"]
+        say(f"{ops} (b = {b}): |O| = {g.size()}, run merges {merged:.0f}, radix sorts {radix:.0f}")
+        assert (merged, radix) == ((1, 0) if b <= 6 else (0, 1))
+        assert_same_operator(g, o, coeff_exact=True)
