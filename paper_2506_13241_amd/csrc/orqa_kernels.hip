@@ -515,40 +515,55 @@ __global__ __launch_bounds__(kThreads) void k_compact(CompactArgs A) {
     for (;;) {
         const uint32_t tile = acquire_tile(ctrl, &sTile);
         if (tile >= ntiles) break;
-        const uint64_t t0 = uint64_t(tile) * kCompactTile;
+        // wave-striped: wave w owns 64 * IPT consecutive strings, element k of
+        // a lane is string seg + 64 k + lane (coalesced loads and stores);
+        // offsets in input order from ballots, wave bases from one block scan
+        const uint64_t seg = uint64_t(tile) * kCompactTile + uint64_t(wave) * 64 * kCompactIPT;
+        const int lane = lane_id();
+        const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
         ulonglong2 xs[kCompactIPT], zs[kCompactIPT];
         CT cs[kCompactIPT][LP];
-        uint32_t alive = 0, gst = 0, nal = 0, ngs = 0;
+        uint64_t balA[kCompactIPT], balG[kCompactIPT];
 #pragma unroll
         for (int k = 0; k < kCompactIPT; ++k) {
-            const uint64_t i = t0 + uint64_t(tid) * kCompactIPT + k;
-            if (i >= n) break;
-            const uint64_t p = vphys(i, nf, A.cap);
-            xs[k] = A.Xin[p];
-            zs[k] = A.Zin[p];
+            const uint64_t i = seg + uint64_t(k) * 64 + lane;
+            bool al = false, gs = false;
+            xs[k] = make_ulonglong2(0, 0);
+            zs[k] = make_ulonglong2(0, 0);
 #pragma unroll
-            for (int a = 0; a < LP; ++a) cs[k][a] = Cin[p * LP + a];
-            bool al = true;
-            if (filt) al = keep_row<CT, LP>(cs[k], sThr);
-            if (A.gscore) {  // learned rule: |c| * min(1, 10^y) > eps * M in some lane
-                const double gw = fmin(1.0, exp10(static_cast<double>(A.gscore[i])));
-                bool keepL = false;
+            for (int a = 0; a < LP; ++a) cs[k][a] = CT(0);
+            if (i < n) {
+                const uint64_t p = vphys(i, nf, A.cap);
+                xs[k] = A.Xin[p];
+                zs[k] = A.Zin[p];
 #pragma unroll
-                for (int a = 0; a < LP; ++a) keepL |= absd(cs[k][a]) * gw > sThrL[a];
-                al = al && keepL;
+                for (int a = 0; a < LP; ++a) cs[k][a] = Cin[p * LP + a];
+                al = true;
+                if (filt) al = keep_row<CT, LP>(cs[k], sThr);
+                if (A.gscore) {  // learned rule: |c| * min(1, 10^y) > eps * M in some lane
+                    const double gw = fmin(1.0, exp10(static_cast<double>(A.gscore[i])));
+                    bool keepL = false;
+#pragma unroll
+                    for (int a = 0; a < LP; ++a) keepL |= absd(cs[k][a]) * gw > sThrL[a];
+                    al = al && keepL;
+                }
+                gs = (i == 0);
+                if (!gs) {
+                    const ulonglong2 xp = A.Xin[vphys(i - 1, nf, A.cap)];
+                    gs = !k_eq(xp, xs[k]);
+                }
             }
-            bool gs = (i == 0);
-            if (!gs) {
-                const ulonglong2 xp = A.Xin[vphys(i - 1, nf, A.cap)];
-                gs = !k_eq(xp, xs[k]);
-            }
-            alive |= uint32_t(al) << k;
-            gst |= uint32_t(gs) << k;
-            nal += al;
-            ngs += gs;
+            balA[k] = __ballot(al);
+            balG[k] = __ballot(gs);
+        }
+        uint32_t nal = 0, ngs = 0;
+#pragma unroll
+        for (int k = 0; k < kCompactIPT; ++k) {
+            nal += uint32_t(__popcll(balA[k]));
+            ngs += uint32_t(__popcll(balG[k]));
         }
         uint32_t totPacked;
-        const uint32_t offPacked = block_excl_scan(nal | (ngs << 16), sWave, totPacked);
+        const uint32_t wOff = __shfl(block_excl_scan(lane == 0 ? (nal | (ngs << 16)) : 0u, sWave, totPacked), 0);
         if (wave == 0) {
             const uint64_t b = lookback_wave(A.status, 1, tile, ep, totPacked & 0xFFFFu, &ctrl->err);
             if (lane_id() == 0) sBase[0] = b;
@@ -557,8 +572,8 @@ __global__ __launch_bounds__(kThreads) void k_compact(CompactArgs A) {
             if (lane_id() == 0) sBase[1] = b;
         }
         __syncthreads();
-        uint64_t o = sBase[0] + (offPacked & 0xFFFFu);
-        uint64_t rk = sBase[1] + (offPacked >> 16);  // group starts before this thread's strings
+        uint64_t oW = sBase[0] + (wOff & 0xFFFFu);  // survivors before element k of this wave
+        uint64_t rW = sBase[1] + (wOff >> 16);      // group starts before element k of this wave
         if (tile == ntiles - 1 && tid == 0) {
             ctrl->nf[A.out_buf] = sBase[0] + (totPacked & 0xFFFFu);
             ctrl->nb[A.out_buf] = 0;
@@ -566,8 +581,11 @@ __global__ __launch_bounds__(kThreads) void k_compact(CompactArgs A) {
         }
 #pragma unroll
         for (int k = 0; k < kCompactIPT; ++k) {
-            rk += (gst >> k) & 1u;
-            if (!((alive >> k) & 1u)) continue;
+            const uint64_t o = oW + uint64_t(__popcll(balA[k] & lt_mask));
+            const uint64_t rk = rW + uint64_t(__popcll(balG[k] & lt_mask)) + ((balG[k] >> lane) & 1ull);
+            oW += uint64_t(__popcll(balA[k]));
+            rW += uint64_t(__popcll(balG[k]));
+            if (!((balA[k] >> lane) & 1ull)) continue;
             ulonglong2 z = zs[k];
             bool neg = false;
             if (A.ngens > 0) {
@@ -594,7 +612,6 @@ __global__ __launch_bounds__(kThreads) void k_compact(CompactArgs A) {
                 Cout[o * LP + a] = v;
                 vmax[a] = fmax(vmax[a], absd(v));
             }
-            ++o;
         }
         __syncthreads();
     }
@@ -879,13 +896,22 @@ __global__ __launch_bounds__(kGsThreads) void k_group_sort(GroupSortArgs A) {
             sB = 0xFFFFFFFFu;
         }
         __syncthreads();
-        // first group start at or after t0 (a) and at or after t1 (b)
-        for (int i = tid; i < kGsMaxGroup; i += kGsThreads) {
+        // first group start at or after t0 (a) and at or after t1 (b), one
+        // chunk of kGsThreads positions at a time until both are found
+        for (int c = 0; c < kGsMaxGroup; c += kGsThreads) {
+            const int i = c + tid;
             const uint64_t p = t0 + i, q = t1 + i;
-            if (p < n && (p == 0 || !k_eq(A.Xs[p], A.Xs[p - 1]))) atomicMin(&sA, uint32_t(i));
-            if (q < n && !k_eq(A.Xs[q], A.Xs[q - 1])) atomicMin(&sB, uint32_t(i));
+            if (i < kGsMaxGroup) {
+                if (p < n && (p == 0 || !k_eq(A.Xs[p], A.Xs[p - 1]))) atomicMin(&sA, uint32_t(i));
+                if (q < n && !k_eq(A.Xs[q], A.Xs[q - 1])) atomicMin(&sB, uint32_t(i));
+            }
+            __syncthreads();
+            const uint64_t next = uint64_t(c) + kGsThreads;
+            const bool doneA = sA != 0xFFFFFFFFu || t0 + next >= n;
+            const bool doneB = t1 >= n || sB != 0xFFFFFFFFu || t1 + next >= n;
+            __syncthreads();  // every thread has read sA and sB before the next chunk updates them
+            if (doneA && doneB) break;
         }
-        __syncthreads();
         // A search window of full length without a group start means a group
         // longer than kGsMaxGroup; one cut short by the end of the operator
         // only means that no group starts there.
