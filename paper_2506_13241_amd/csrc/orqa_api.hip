@@ -672,7 +672,9 @@ int run_rx_graph(ps_handle* h, const std::vector<GateTrig>& trigs, double pend0,
 // Sort of a general gate's branch output (buffer b) whose entries carry run
 // tags (0 parents, 1 + class children, at most 2^bits classes): one stable
 // radix pass on the tag gathers the runs, each sorted by (x, z); a tree of
-// pairwise merges then sorts the whole.  Result buffer in *result.
+// pairwise merges then sorts the whole.  Result buffer in *result.  Returns
+// kUseRadix, with nothing launched, when the split buffer cannot be had.
+constexpr int kUseRadix = 1;
 int merge_gen_runs(ps_handle* h, int b, int bits, int* result) {
     Ctrl c;
     int rc = read_ctrl(h, &c);
@@ -688,7 +690,7 @@ int merge_gen_runs(ps_handle* h, int b, int bits, int* result) {
         const size_t words = need + need / 4;
         if (hipMalloc(reinterpret_cast<void**>(&h->msplit), words * 8) != hipSuccess) {
             (void)hipGetLastError();
-            return fail(PS_ERR_CAPACITY, "hipMalloc failed for %zu merge splits", words);
+            return kUseRadix;  // the radix sort needs no memory of its own
         }
         h->msplit_words = words;
     }
@@ -858,7 +860,11 @@ int sort_by_rank_z(ps_handle* h, int b, int* result, bool full_key = false, bool
         HIP_TRY(hipMemcpyAsync(&h->ctrl->aux[2], &zero, 8, hipMemcpyHostToDevice, h->stream));
         HIP_TRY(hipMemcpyAsync(&h->ctrl->nf[1 - b], &zero, 8, hipMemcpyHostToDevice, h->stream));
     }
-    if (full_key && run_bits >= 0) return merge_gen_runs(h, b, run_bits, result);
+    if (full_key && run_bits >= 0) {
+        rc = merge_gen_runs(h, b, run_bits, result);
+        if (rc != kUseRadix) return rc;
+        *result = b;
+    }
     const int kind = full_key ? 1 : 0;
     int cls = 0;
     while (cls < 63 && (uint64_t(2) << cls) <= n) ++cls;
