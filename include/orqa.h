@@ -106,7 +106,10 @@ int pauli_sum_destroy(ps_handle* h);
  * (e.g. RZZ(-pi/2) layers) are fused into one pass plus one re-sort; sigma_x
  * rotations on consecutive qubits q, q+1, ... (each layer ascending, starting at
  * qubit 0) run as one streaming pass per gate.  Any other generator takes the
- * general branch / sort / reduce path.
+ * general path: a branch pass (parent part and child per string), a sort by
+ * key (inside each x-group for Z-only generators; a gather and pairwise merge
+ * of the branch's sorted runs when the generator flips few key bits; else the
+ * radix sort) and a pass summing the entries of equal keys.
  * On PS_ERR_CAPACITY the gates before the failing one have been applied
  * (pauli_sum_gates_applied tells how many) and the handle stays usable.
  */
