@@ -193,6 +193,12 @@ __device__ __forceinline__ uint64_t lookback_wave(uint64_t* st, uint64_t stride,
     return excl;
 }
 
+// Back-off between polls of the two-level look-back, in units of 64 clocks.
+// Pollers of one prefix frontier all read the same few status lines, so a
+// longer back-off relieves those lines more than it delays the poller
+// (measured on the RX merge: 16 -> 40 is 3.5% faster, 100 slower again).
+constexpr int kLb2Sleep = 40;
+
 // Two-level decoupled look-back.  Tiles form groups of 64; the last tile of
 // a group also publishes the group's aggregate (before its own look-back) and
 // the group's inclusive prefix (after it) in gst[group].  A tile sums the
@@ -235,7 +241,7 @@ __device__ __forceinline__ uint64_t lookback_wave2(uint64_t* st, uint64_t* gst, 
                 timed_out = true;
                 break;
             }
-            __builtin_amdgcn_s_sleep(16);
+            __builtin_amdgcn_s_sleep(kLb2Sleep);
         }
         const uint64_t gsum = wave_sum_u64((!timed_out && lane <= fi) ? (v & kValMask) : 0ull);
         if (lane == 0 && !timed_out) st_rel(gst + grp, st_pack(ep, fi < 64 ? 2u : 1u, gsum));
@@ -264,7 +270,7 @@ __device__ __forceinline__ uint64_t lookback_wave2(uint64_t* st, uint64_t* gst, 
                 timed_out = true;
                 break;
             }
-            __builtin_amdgcn_s_sleep(16);
+            __builtin_amdgcn_s_sleep(kLb2Sleep);
         }
         if (!timed_out) {
             excl += wave_sum_u64((in && lane <= fi) ? (v & kValMask) : 0ull);
@@ -296,7 +302,7 @@ __device__ __forceinline__ uint64_t lookback_wave2(uint64_t* st, uint64_t* gst, 
                     timed_out = true;
                     break;
                 }
-                __builtin_amdgcn_s_sleep(16);
+                __builtin_amdgcn_s_sleep(kLb2Sleep);
             }
             if (timed_out) break;
             excl += wave_sum_u64(lane <= fi ? (v & kValMask) : 0ull);
