@@ -143,8 +143,8 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(each MI355X would hold one shard of the operator; see DESIGN.md).", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path (each MI355X "
+              "would hold the strings of one hash class of the z mask).", file=sys.stderr)
         sys.exit(2)
 
     import torch
