@@ -1,14 +1,14 @@
 """What the trained scorer gains over plain magnitude truncation (needs a GPU).
 
 127-qubit kicked Ising, theta_h = 0.8, observable Z62, 10 Trotter steps.  The
-judge is the magnitude run at eps0 = 1e-5 (the error reference; the exact
-value is out of reach at this size).  The committed network
+error reference is the magnitude run at eps0 = 1e-5 (the exact value is out
+of reach at this size).  The committed network
 (paper_2506_13241_amd/data, trained by paper_2506_13241_amd.train_scorer on
 strings from 8-step runs, horizon-3 labels) is compared at matched operating
 points: learned truncation at eps must keep fewer strings summed over the
 steps than magnitude truncation at 10 eps, with a smaller worst and mean
-|<Z62> - judge|.  The judge is itself a magnitude run, which favours the
-magnitude side of the comparison."""
+|<Z62> - reference|.  The reference is itself a magnitude run, which favours
+the magnitude side of the comparison."""
 
 import os
 import sys
@@ -49,12 +49,12 @@ def test_learned_truncation_keeps_fewer_strings_at_lower_error():
         op.close()
         return np.array(ez), int(np.sum(sz))
 
-    judge, judge_size = run(1e-5, P.PS_TRUNC_MAGNITUDE)
-    say(f"judge eps 1e-5: sum|O| = {judge_size:.3e}")
+    ref, ref_size = run(1e-5, P.PS_TRUNC_MAGNITUDE)
+    say(f"reference eps 1e-5: sum|O| = {ref_size:.3e}")
     for eps in (1e-5, 5e-6):
         ez_m, n_m = run(10 * eps, P.PS_TRUNC_MAGNITUDE)
         ez_l, n_l = run(eps, P.PS_TRUNC_LEARNED)
-        em, el = np.abs(ez_m - judge), np.abs(ez_l - judge)
+        em, el = np.abs(ez_m - ref), np.abs(ez_l - ref)
         say(f"magnitude {10 * eps:g}: sum|O| {n_m:.3e} max {em.max():.2e} mean {em.mean():.2e} | "
             f"learned {eps:g}: sum|O| {n_l:.3e} max {el.max():.2e} mean {el.mean():.2e}")
         assert n_l < 0.75 * n_m
