@@ -243,3 +243,23 @@ def test_run_merge_up_to_65_runs_on_127_qubits():
         say(f"{ops} (b = {b}): |O| = {g.size()}, run merges {merged:.0f}, radix sorts {radix:.0f}")
         assert (merged, radix) == ((1, 0) if b <= 6 else (0, 1))
         assert_same_operator(g, o, coeff_exact=True)
+
+
+def test_general_gates_on_word_boundaries_of_a_128_qubit_register():
+    """Generators on qubits 0, 63, 64 and 127 (the edges of the two mask
+    words) on a full 128-qubit register, through the run merge (b <= 6) and
+    the radix sort (b = 8), bit for bit against the oracle."""
+    n = 128
+    edge = [0, 1, 62, 63, 64, 65, 126, 127]
+    terms, coeffs = w.random_pauli_set(n, 20000, seed=97, support=edge)
+    specs = [({63: "Y", 64: "X"}, 0.5), ({0: "Z", 127: "Y"}, 1.2), ({63: "X", 64: "Z", 127: "X"}, 0.35),
+             ({0: "Y", 63: "Y", 64: "Y", 127: "Y"}, 0.8)]
+    g, o = _both(n, terms, coeffs)
+    for ops, th in specs:
+        gate = w.GateList(w.pauli_words(n, ops)[None, :], np.array([[th]]))
+        g.apply_rotation_layer(gate, 1e-7)
+        o.apply(gate, 1e-7)
+        assert_same_operator(g, o, coeff_exact=True)
+    st = g.stats()
+    say(f"128-q word edges: |O| = {g.size()}, run merges {st['run_merges']:.0f}, radix sorts {st['radix_sorts']:.0f}")
+    assert st["run_merges"] == 3 and st["radix_sorts"] == 1
