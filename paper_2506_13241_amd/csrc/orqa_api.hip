@@ -550,9 +550,8 @@ GenArgs gen_args(ps_handle* h, int in, int out, int mx_in, int mx_out) {
 }
 
 // General gate, first half: parents and children of every string, in input
-// order, in true x (the stored rotation is undone) unless x_J = 0 (then x as
-// stored); tagged by sorted run when the generator flips few key bits and the
-// output keeps the input's order.
+// order and in the stored x frame; tagged by sorted run when the generator
+// flips few key bits.
 int enqueue_gen_branch(ps_handle* h, int in, int out, int mx_in, double eps_in, const Stage& st) {
     GenArgs a = gen_args(h, in, out, mx_in, 1 - mx_in);
     a.eps_in = eps_in;
@@ -561,10 +560,8 @@ int enqueue_gen_branch(ps_handle* h, int in, int out, int mx_in, double eps_in, 
     a.xj1 = st.gen.x[1];
     a.zj0 = st.gen.z[0];
     a.zj1 = st.gen.z[1];
-    a.keep_rot = (st.gen.x[0] | st.gen.x[1]) == 0 ? 1 : 0;
     // children form at most 2^b sorted runs (b = key bits the generator
-    // flips) when the output is written in the order the input is sorted in:
-    // x as stored (x_J = 0) or no stored rotation
+    // flips): the output is written in the stored frame the input is sorted in
     h->gen_run_bits = -1;
     const int b = __builtin_popcountll(st.gen.x[0]) + __builtin_popcountll(st.gen.x[1]) +
                   __builtin_popcountll(st.gen.z[0]) + __builtin_popcountll(st.gen.z[1]);
@@ -572,13 +569,14 @@ int enqueue_gen_branch(ps_handle* h, int in, int out, int mx_in, double eps_in, 
     // the radix sort's byte digits of x and z (fewer on small registers)
     const int merge_passes = 1 + (b + 1);
     const int radix_passes = 2 * ((h->nq + 7) / 8);
-    if ((a.keep_rot || h->xrot == 0) && b <= kRunMaxBits && (b <= 4 || merge_passes < radix_passes)) {
+    if (b <= kRunMaxBits && (b <= 4 || merge_passes < radix_passes)) {
         int q = 0;
         for (int isz = 0; isz < 2; ++isz)
             for (int bit = 0; bit < 128; ++bit) {
                 const uint64_t* m = isz ? st.gen.z : st.gen.x;
                 if ((m[bit >> 6] >> (bit & 63)) & 1u) {
-                    a.run_pos[q] = static_cast<uint8_t>(bit);
+                    // x bits sit at their stored position, bit - xrot (mod n)
+                    a.run_pos[q] = static_cast<uint8_t>(isz ? bit : (bit - h->xrot + h->nq) % h->nq);
                     a.run_isz[q] = static_cast<uint8_t>(isz);
                     ++q;
                 }
@@ -1268,7 +1266,6 @@ int apply_rotation_layer(ps_handle* h, const ps_pauli* gens, const double* theta
             t.any_c = any_c;
             t.any_s = any_s;
             stages.push_back(s);
-            if ((G.x[0] | G.x[1]) != 0) xrot = 0;  // x_J = 0 keeps the stored rotation, else x is unrotated
             ++g;
         }
     }
@@ -1325,8 +1322,7 @@ int apply_rotation_layer(ps_handle* h, const ps_pauli* gens, const double* theta
                 rc = enqueue_gen_branch(h, in, out, mx_in, h->pend, s);
                 if (rc) return rc;
                 h->cur = out;
-                gen_zonly = (s.gen.x[0] | s.gen.x[1]) == 0;
-                if (!gen_zonly) h->xrot = 0;
+                gen_zonly = (s.gen.x[0] | s.gen.x[1]) == 0;  // outputs keep the stored frame
                 h->pend = -1.0;
                 gen_after = true;
                 ++si;

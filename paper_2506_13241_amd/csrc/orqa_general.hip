@@ -65,10 +65,10 @@ __device__ __forceinline__ void scan_striped4(const uint32_t (&c)[4], uint32_t* 
 
 // Branch: reads the (virtual, x-rotated) input, applies the pending truncation,
 // writes parents and children compacted to the front of the output, in input
-// order (each parent before its child), in true x (or, when x_J = 0, with x
-// as stored: then every output stays in its parent's x-group and the groups
-// keep their order).  Output offsets by a two-level decoupled look-back over
-// tiles.
+// order (each parent before its child), with x in the stored frame (the sign
+// algebra runs on the true x).  For x_J = 0 every output stays in its
+// parent's x-group and the groups keep their order.  Output offsets by a
+// two-level decoupled look-back over tiles.
 template <typename CT, int LP>
 __global__ __launch_bounds__(kThreads) void k_gen_branch(GenArgs A, GateTrig g) {
     __shared__ uint32_t sWave[4];
@@ -88,6 +88,8 @@ __global__ __launch_bounds__(kThreads) void k_gen_branch(GenArgs A, GateTrig g) 
     if (tid < LP) sThr[tid] = filt ? A.eps_in * bits_to_d(ctrl->maxbits[A.mx_in][tid]) : -1.0;
     __syncthreads();
     const ulonglong2 xj = make_ulonglong2(A.xj0, A.xj1), zj = make_ulonglong2(A.zj0, A.zj1);
+    // the generator's x in the stored frame (stored x = true x rotated right by xrot)
+    const ulonglong2 xjs = rotl_n(xj, (A.nq - A.xrot) % A.nq, A.nq);
 
     for (;;) {
         const uint32_t tile = acquire_tile(ctrl, &sTile);
@@ -137,7 +139,7 @@ __global__ __launch_bounds__(kThreads) void k_gen_branch(GenArgs A, GateTrig g) 
             const uint64_t i = t0 + uint64_t(k) * kThreads + tid;
             const CT* ce = Cin + vphys(i, nf, A.cap) * LP;
             const ulonglong2 xt = rotl_n(xs[k], A.xrot, A.nq);
-            const ulonglong2 xw = A.keep_rot ? xs[k] : xt;  // x as written
+            const ulonglong2 xw = xs[k];  // x as stored: outputs keep the stored frame
             const bool anti = ((k_popc_and(xt, zj) + k_popc_and(zs[k], xj)) & 1) != 0;
             if (!anti) {  // commutes: unchanged
                 if (o < A.cap) {
@@ -165,7 +167,7 @@ __global__ __launch_bounds__(kThreads) void k_gen_branch(GenArgs A, GateTrig g) 
                 const ulonglong2 zc = make_ulonglong2(zs[k].x ^ zj.x, zs[k].y ^ zj.y);
                 const bool neg = gen_child_negative(xt, zs[k], xc, zc, xj, zj);
                 if (o < A.cap) {
-                    A.Xout[o] = A.keep_rot ? xw : xc;  // keep_rot only for x_J = 0: same x
+                    A.Xout[o] = make_ulonglong2(xw.x ^ xjs.x, xw.y ^ xjs.y);
                     A.Zout[o] = zc;
 #pragma unroll
                     for (int a = 0; a < LP; ++a) Cout[o * LP + a] = Arith<CT>::scale_s(g, a, ce[a], neg);

@@ -198,10 +198,9 @@ struct GenArgs {
     double eps_in;  // pending truncation threshold of the input (<= 0: none)
     int xrot, nq;
     uint64_t xj0, xj1, zj0, zj1;  // the generator sigma_J
-    int keep_rot;                  // x_J = 0: write x as stored (rotated), keep the x-group order
     // run tags (NULL: none): 0 for a parent, 1 + class for a child, the class
     // being the parent's bits at the generator's run_bits key positions
-    // (run_pos, in z when run_isz, else in x as written)
+    // (run_pos, in z when run_isz, else in the stored x)
     uint32_t* Tout;
     int run_bits;
     uint8_t run_pos[6];

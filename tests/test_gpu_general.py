@@ -263,3 +263,21 @@ def test_general_gates_on_word_boundaries_of_a_128_qubit_register():
     st = g.stats()
     say(f"128-q word edges: |O| = {g.size()}, run merges {st['run_merges']:.0f}, radix sorts {st['radix_sorts']:.0f}")
     assert st["run_merges"] == 3 and st["radix_sorts"] == 1
+
+
+def test_general_gate_with_x_letters_inside_an_rx_run_keeps_the_stream():
+    """A general gate with X and Y letters between RX gates writes its
+    outputs in the stored (rotated) x frame, so the RX run resumes on its
+    streaming path: four RX gates stream, the general gate takes the run
+    merge, bit for bit against the oracle."""
+    n = 12
+    terms, coeffs = w.random_pauli_set(n, 5000, seed=99)
+    seq = [({0: "X"}, 0.3), ({1: "X"}, 0.4), ({4: "Y", 6: "X"}, 0.7), ({2: "X"}, 0.5), ({3: "X"}, 0.6)]
+    gl = w.GateList(np.stack([w.pauli_words(n, ops) for ops, _ in seq]), np.array([[th] for _, th in seq]))
+    g, o = _both(n, terms, coeffs)
+    g.apply_rotation_layer(gl, 1e-6)
+    o.apply(gl, 1e-6)
+    st = g.stats()
+    say(f"stream across a general gate: rx launches {st['rx_launches']:.0f}, run merges {st['run_merges']:.0f}")
+    assert st["rx_launches"] == 4 and st["run_merges"] == 1
+    assert_same_operator(g, o, coeff_exact=True)
