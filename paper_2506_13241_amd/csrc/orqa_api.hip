@@ -318,9 +318,12 @@ int ev_begin(ps_handle* h, int kind, size_t* slot) {
     *slot = SIZE_MAX;
     if (!h->timing) return PS_OK;
     if (h->ev_used + 2 > h->ev_pool.size()) {
+        // timing-only events: no system-scope fence (cache writeback and
+        // invalidate) when they complete; they are read after a stream
+        // synchronisation
         for (int i = 0; i < 64; ++i) {
             hipEvent_t e;
-            HIP_TRY(hipEventCreate(&e));
+            HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
             h->ev_pool.push_back(e);
         }
         h->ev_kind.resize(h->ev_pool.size() / 2);
@@ -899,8 +902,8 @@ int sort_by_rank_z(ps_handle* h, int b, int* result, bool full_key = false, bool
                            h->stream));
     const bool tune = h->sort_force < 0 && n >= kSortTuneMin;
     if (tune && !h->sort_ev[0]) {
-        HIP_TRY(hipEventCreate(&h->sort_ev[0]));
-        HIP_TRY(hipEventCreate(&h->sort_ev[1]));
+        HIP_TRY(hipEventCreateWithFlags(&h->sort_ev[0], hipEventDisableSystemFence));
+        HIP_TRY(hipEventCreateWithFlags(&h->sort_ev[1], hipEventDisableSystemFence));
     }
     if (tune) HIP_TRY(hipEventRecord(h->sort_ev[0], h->stream));
     int src = b;
