@@ -191,7 +191,8 @@ int pauli_sum_histogram(ps_handle* h, int lane, const double* edges, int n_bins,
 /*
  * pauli_sum_set_sort_config -- digit width and tile size of the radix sort
  * (the re-sort after a Clifford layer, Eq. (u), when its x-groups are too large
- * for the in-group sort, and the merge of general gates, Eq. update_rule).
+ * for the in-group sort, and the sort of general gates, Eq. update_rule, whose
+ * generators flip too many key bits for the run merge).
  * (digit_bits, items_per_thread) is one of (8, 8), (8, 16), (7, 16), (6, 16),
  * (7, 8), (6, 8); a tile holds 256 * items_per_thread strings.  (0, 0), the
  * default, tunes online: the first sorts of each size class (powers of two of
@@ -236,8 +237,12 @@ int pauli_sum_load_scorer(ps_handle* h, const ps_scorer* s);
  *   gates          gates applied
  *   rx_launches    streaming RX merge launches; rx_in / rx_out strings read /
  *                  written by them; rx_ms their summed kernel time
- *   cliff_launches fused Clifford / compaction launches, cliff_ms their time
- *   sort_passes    radix-sort passes, sort_ms their time
+ *   cliff_launches fused Clifford / compaction launches; cliff_ms their time
+ *                  plus that of the branch and equal-key passes of general
+ *                  gates
+ *   sort_passes    sort passes (in-group sorts, radix passes, run gathers and
+ *                  merge levels), sort_elems the strings they moved, sort_ms
+ *                  their time
  *   bytes_per_string  key + coefficient bytes of one stored string
  *   graph_replays, graph_captures  runs of RX gates replayed from / captured
  *                  into HIP graphs (pauli_sum_set_graphs)
