@@ -59,3 +59,27 @@ def test_committed_weights_load():
     assert params.shape == (S.N_PARAMS,) and np.all(np.isfinite(params))
     assert meta["lattice"] == "eagle127" and meta["obs"] == "62" and float(meta["theta"]) == 0.8
     assert float(meta["loss_last"]) < 0.25 * float(meta["target_sd"]) ** 2
+
+
+def test_stratified_sample_spreads_over_log_magnitude_bins():
+    """The training sampler takes up to count/bins strings from each of the
+    log10(|c|/max|c|) bins between log10(eps) and 0, without repeats, and
+    nothing from an all-zero operator."""
+    from paper_2506_13241_amd.train_scorer import stratified_sample
+    rng = np.random.default_rng(5)
+    c = np.concatenate([np.full(1000, 1e-5), np.full(10, 0.5), np.full(3000, 2e-2), [1.0]])
+    idx = stratified_sample(c, 120, 1e-6, rng, bins=6)
+    assert len(np.unique(idx)) == len(idx) and np.all(np.diff(idx) > 0)
+    r = np.log10(np.abs(c[idx]))
+    counts = np.histogram(r, bins=np.linspace(-6, 0, 7))[0]
+    # bins holding enough strings give count / bins = 20 each; the 0.5 and
+    # 1.0 strings share the top bin (11 strings)
+    assert counts.tolist() == [0, 20, 0, 0, 20, 11]
+    assert len(stratified_sample(np.zeros(10), 5, 1e-3, rng)) == 0
+
+
+def test_log_density_edges():
+    from paper_2506_13241_amd.diagnostics import log_density_edges
+    e = log_density_edges(1e-6, 70)
+    assert len(e) == 71 and abs(e[0] - 1e-7) < 1e-20 and e[-1] == 1.0
+    assert np.allclose(np.diff(np.log10(e)), 0.1)
