@@ -354,9 +354,58 @@ def pauli_sum_load_scorer(ps: PauliSum, scorer: PsScorer):
     return ps.load_scorer(scorer)
 
 
+def pauli_sum_set_sort_config(ps: PauliSum, digit_bits=0, items_per_thread=0):
+    return ps.set_sort_config(digit_bits, items_per_thread)
+
+
+def pauli_sum_set_graphs(ps: PauliSum, enable=True):
+    return ps.set_graphs(enable)
+
+
+def pauli_sum_set_timing(ps: PauliSum, enable=True):
+    return ps.set_timing(enable)
+
+
+def pauli_sum_stats(ps: PauliSum, reset=False) -> dict:
+    return ps.stats(reset)
+
+
+def pauli_sum_gates_applied(ps: PauliSum) -> int:
+    return ps.gates_applied()
+
+
 def ps_scorer_create(n_qubits, qmask, letters, scales, stream=None) -> PsScorer:
     return PsScorer(n_qubits, qmask, letters, scales, stream=stream)
 
 
 def ps_scorer_destroy(s: PsScorer):
     s.close()
+
+
+def ps_last_error() -> str:
+    """Message of the calling thread's last failed library call."""
+    return load_library().ps_last_error().decode()
+
+
+def ps_scorer_set_params(s: PsScorer, params):
+    return s.set_params(params)
+
+
+def ps_scorer_get_params(s: PsScorer) -> np.ndarray:
+    return s.get_params()
+
+
+def ps_scorer_set_data(s: PsScorer, keys, targets):
+    return s.set_data(keys, targets)
+
+
+def ps_scorer_forward(s: PsScorer, features: bool = False):
+    return s.forward(features)
+
+
+def ps_scorer_loss_grad(s: PsScorer, grad: bool = True):
+    return s.loss_grad(grad)
+
+
+def ps_scorer_adam_step(s: PsScorer, lr: float):
+    return s.adam_step(lr)

@@ -86,3 +86,9 @@ def test_scorer_and_graph_entry_points_validate_before_device_calls(lib):
     assert L.pauli_sum_load_scorer(None, None) == P.PS_ERR_INVALID
     assert L.pauli_sum_set_graphs(None, 1) == P.PS_ERR_INVALID
     assert L.pauli_sum_set_timing(None, 1) == P.PS_ERR_INVALID
+
+
+def test_binding_has_every_entry_point_by_name():
+    """The Python binding offers every C entry point under its own name."""
+    import paper_2506_13241_amd as P
+    assert [n for n in P.EXPORTED_SYMBOLS if not callable(getattr(P, n, None))] == []
