@@ -300,11 +300,6 @@ int alloc_buffers(ps_handle* h, size_t cap) {
     return PS_OK;
 }
 
-int sync(ps_handle* h) {
-    HIP_TRY(hipStreamSynchronize(h->stream));
-    return PS_OK;
-}
-
 int ev_collect(ps_handle* h);
 
 int read_ctrl(ps_handle* h, Ctrl* c) {
@@ -972,14 +967,6 @@ int materialize(ps_handle* h) {
     h->mx = mx_out;
     h->pend = -1.0;
     return check_no_error(h, "truncation");
-}
-
-int set_max_from_host(ps_handle* h, int slot, const std::vector<double>& mx) {
-    std::vector<uint64_t> bits(kMaxLanes, 0);
-    for (int a = 0; a < h->L; ++a) std::memcpy(&bits[a], &mx[a], 8);
-    HIP_TRY(hipMemcpyAsync(&h->ctrl->maxbits[slot][0], bits.data(), kMaxLanes * 8, hipMemcpyHostToDevice, h->stream));
-    HIP_TRY(hipStreamSynchronize(h->stream));
-    return PS_OK;
 }
 
 }  // namespace
