@@ -274,7 +274,7 @@ __global__ void k_scorer_loss(const float* __restrict__ y, const float* __restri
     s[threadIdx.x] = acc;
     __syncthreads();
     for (int o = kThreads / 2; o > 0; o >>= 1) {
-        if (threadIdx.x < o) s[threadIdx.x] += s[threadIdx.x + o];
+        if (int(threadIdx.x) < o) s[threadIdx.x] += s[threadIdx.x + o];
         __syncthreads();
     }
     if (threadIdx.x == 0) out[0] = s[0] / double(n);
