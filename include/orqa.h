@@ -184,7 +184,12 @@ int pauli_sum_export(ps_handle* h, ps_pauli* keys, void* coeffs, size_t cap, siz
  * strictly increasing, 1 <= n_bins <= 4096); bin membership is decided by
  * comparing the coefficient with max|O| * edges[k] in binary64.  counts (host
  * out, n_bins + 2): the bins, then the values below edges[0], then those above
- * edges[n_bins].  Applies a pending truncation first (as export does).
+ * edges[n_bins].  Strings a pending truncation drops are not counted (the
+ * counts equal those of the truncated operator).  Device memory for the
+ * edges and counters is allocated and freed by each call.
+ * Errors: PS_ERR_INVALID (NULL pointer, lane out of range, n_bins outside
+ * 1..4096, edges not increasing), PS_ERR_NONFINITE (an edge), PS_ERR_CAPACITY
+ * (hipMalloc failed); the operator is never changed.
  */
 int pauli_sum_histogram(ps_handle* h, int lane, const double* edges, int n_bins, int is_signed, uint64_t* counts);
 
@@ -214,6 +219,21 @@ int pauli_sum_set_sort_config(ps_handle* h, int digit_bits, int items_per_thread
  * handle's stream.  enable == 0 drops the cached graphs.
  */
 int pauli_sum_set_graphs(ps_handle* h, int enable);
+
+/*
+ * Look-back epoch (for tests of its guard).  The single-pass kernels that
+ * assign output offsets (stream compaction, Algorithm 1's truncation loop,
+ * and the merge of Eq. update_rule) publish per-tile status words tagged with
+ * the low 24 bits of a launch counter, the epoch; words of other launches
+ * read as not ready, so the words are never cleared between launches.  The
+ * library clears them and restarts the epoch at 1 before the tag can wrap.
+ *   pauli_sum_set_lookback_epoch  clear the status words and restart the
+ *                                 epoch at `epoch` (1 .. 2^24 - 3, else
+ *                                 PS_ERR_INVALID), e.g. just below the wrap.
+ *   pauli_sum_lookback_epoch      read the current epoch (host out).
+ */
+int pauli_sum_set_lookback_epoch(ps_handle* h, uint32_t epoch);
+int pauli_sum_lookback_epoch(ps_handle* h, uint32_t* epoch);
 
 typedef struct ps_scorer ps_scorer;
 int ps_scorer_create(int n_qubits, const uint64_t* qmask, const uint8_t* letters, const float* scales,

@@ -28,6 +28,7 @@ EXPORTED_SYMBOLS = (
     "ps_scorer_create", "ps_scorer_destroy", "ps_scorer_set_params", "ps_scorer_get_params", "ps_scorer_set_data",
     "ps_scorer_forward", "ps_scorer_loss_grad", "ps_scorer_adam_step", "pauli_sum_set_graphs",
     "pauli_sum_histogram", "pauli_sum_set_sort_config",
+    "pauli_sum_set_lookback_epoch", "pauli_sum_lookback_epoch",
 )
 N_SCORER_PARAMS = 37249
 SORT_CONFIGS = ((8, 8), (8, 16), (7, 16), (6, 16), (7, 8), (6, 8))  # (digit bits, items per thread)
@@ -86,6 +87,8 @@ def load_library(path: str = LIB_PATH):
         "ps_last_error": (ctypes.c_char_p, []),
         "pauli_sum_set_graphs": (I, [P, I]),
         "pauli_sum_histogram": (I, [P, I, P, I, I, P]),
+        "pauli_sum_set_lookback_epoch": (I, [P, ctypes.c_uint32]),
+        "pauli_sum_lookback_epoch": (I, [P, ctypes.POINTER(ctypes.c_uint32)]),
         "pauli_sum_set_sort_config": (I, [P, I, I]),
         "ps_scorer_create": (I, [I, P, P, P, P, ctypes.POINTER(P)]),
         "ps_scorer_destroy": (I, [P]),
@@ -232,14 +235,15 @@ class PauliSum:
         _check(_lib.pauli_sum_histogram(self._h, lane, _ptr(e), e.size - 1, int(signed), _ptr(out)))
         return out
 
-    def density(self, n_bins: int = 200, signed: bool = True, lane: int = 0):
-        """D_t(x): normalized histogram of x = c / max|c| on [-1, 1] (signed) or
-        [0, 1]; returns (bin centres, density)."""
-        edges = np.linspace(-1.0 if signed else 0.0, 1.0, n_bins + 1)
-        cnt = self.histogram(edges, signed, lane)[:n_bins].astype(np.float64)
-        width = edges[1] - edges[0]
-        total = cnt.sum()
-        return 0.5 * (edges[1:] + edges[:-1]), (cnt / (total * width) if total else cnt)
+    def set_lookback_epoch(self, epoch: int):
+        """Clear the look-back status words and restart their epoch (tests of the wrap guard)."""
+        _check(_lib.pauli_sum_set_lookback_epoch(self._h, int(epoch)))
+        return self
+
+    def lookback_epoch(self) -> int:
+        e = ctypes.c_uint32()
+        _check(_lib.pauli_sum_lookback_epoch(self._h, ctypes.byref(e)))
+        return int(e.value)
 
     def load_scorer(self, scorer: "PsScorer"):
         """Copy a scorer's network into this handle (for PS_TRUNC_LEARNED)."""
@@ -348,6 +352,14 @@ def pauli_sum_export(ps: PauliSum):
 
 def pauli_sum_histogram(ps: PauliSum, edges, signed=True, lane=0):
     return ps.histogram(edges, signed, lane)
+
+
+def pauli_sum_set_lookback_epoch(ps: PauliSum, epoch: int):
+    return ps.set_lookback_epoch(epoch)
+
+
+def pauli_sum_lookback_epoch(ps: PauliSum) -> int:
+    return ps.lookback_epoch()
 
 
 def pauli_sum_load_scorer(ps: PauliSum, scorer: PsScorer):

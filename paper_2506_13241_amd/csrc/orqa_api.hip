@@ -115,6 +115,11 @@ struct Stage {
 
 struct ps_handle {
     int nq = 0, L = 1, LP = 1, dtype = PS_F64;
+    int dev = 0;        // HIP device current at creation (holds the buffers)
+    // look-back launches since the status words were last cleared; the device
+    // epoch equals 1 + this count, and the words are cleared before it reaches
+    // 2^24 (the width of the epoch tag in a status word)
+    uint64_t lb_count = 0;
     size_t csize = 8;  // bytes per coefficient row
     size_t cap = 0;
     Buf buf[2] = {};
@@ -441,6 +446,32 @@ int check_no_error(ps_handle* h, const char* what) {
     return PS_OK;
 }
 
+// Status words carry the low 24 bits of the launch epoch; a word written 2^24
+// look-back launches earlier and not since would read as current.  Before the
+// epoch gets there, clear every status word and restart the epoch at 1.  Must
+// be called before enqueueing `k` look-back launches, outside stream capture.
+constexpr uint64_t kEpochLimit = (uint64_t(1) << 24) - 2;
+
+int lb_reserve(ps_handle* h, uint64_t k) {
+    if (h->lb_count + k < kEpochLimit) {
+        h->lb_count += k;
+        return PS_OK;
+    }
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    HIP_TRY(launch_fill_u64(h->status, 0ull, h->status_words, h->stream));
+    const uint32_t one = 1;
+    HIP_TRY(hipMemcpyAsync(&h->ctrl->epoch, &one, sizeof one, hipMemcpyHostToDevice, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    h->lb_count = k;
+    return PS_OK;
+}
+
+#define LB_RESERVE(h, k)                \
+    do {                                \
+        const int _rc = lb_reserve(h, k); \
+        if (_rc) return _rc;            \
+    } while (0)
+
 // ---------------------------------------------------------------- stages
 
 int enqueue_compact(ps_handle* h, int in, int out, int mx_in, int mx_out, double eps_in, const CliffGen* gens,
@@ -492,12 +523,13 @@ int enqueue_compact(ps_handle* h, int in, int out, int mx_in, int mx_out, double
     size_t slot;
     int rc = ev_begin(h, 1, &slot);
     if (rc) return rc;
+    LB_RESERVE(h, 1);
     HIP_TRY(launch_compact(a, h->dtype, h->LP, h->stream, h->grid));
     return ev_end(h, slot);
 }
 
 int enqueue_rx(ps_handle* h, int in, int out, int mx_in, int mx_out, double eps_in, const GateTrig& g,
-               hipStream_t stream = nullptr, bool timed = true) {
+               hipStream_t stream = nullptr, bool timed = true, bool capturing = false) {
     if (!stream) stream = h->stream;
     RxArgs a{};
     a.ctrl = h->ctrl;
@@ -517,6 +549,7 @@ int enqueue_rx(ps_handle* h, int in, int out, int mx_in, int mx_out, double eps_
     a.max_tiles = h->max_tiles;
     a.eps_in = eps_in;
     a.nq = h->nq;
+    if (!capturing) LB_RESERVE(h, 1);  // a captured run reserves its launches at replay
     HIP_TRY(launch_rx_partition(a, stream));
     size_t slot = SIZE_MAX;
     if (timed) {
@@ -586,6 +619,7 @@ int enqueue_gen_branch(ps_handle* h, int in, int out, int mx_in, double eps_in, 
     size_t slot;
     int rc = ev_begin(h, 1, &slot);
     if (rc) return rc;
+    LB_RESERVE(h, 1);
     HIP_TRY(launch_gen_branch(a, st.trig, h->dtype, h->LP, h->stream, h->grid));
     return ev_end(h, slot);
 }
@@ -597,6 +631,7 @@ int enqueue_gen_reduce(ps_handle* h, int in, int out, int mx_out) {
     size_t slot;
     int rc = ev_begin(h, 1, &slot);
     if (rc) return rc;
+    LB_RESERVE(h, 1);
     HIP_TRY(launch_gen_reduce(a, h->dtype, h->LP, h->stream, h->grid));
     return ev_end(h, slot);
 }
@@ -628,6 +663,7 @@ int run_rx_graph(ps_handle* h, const std::vector<GateTrig>& trigs, double pend0,
     key = fnv1a(key, &pend0, sizeof pend0);
     key = fnv1a(key, &eps, sizeof eps);
     for (const GateTrig& t : trigs) key = fnv1a(key, &t, sizeof t);
+    LB_RESERVE(h, n);  // the run's look-back launches, captured or replayed
     for (const auto& e : h->graph_cache)
         if (e.key == key && e.n_stages == n) {
             HIP_TRY(hipGraphLaunch(e.exec, h->stream));
@@ -638,7 +674,7 @@ int run_rx_graph(ps_handle* h, const std::vector<GateTrig>& trigs, double pend0,
     HIP_TRY(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
     int cur = h->cur, mx = h->mx, rc = PS_OK;
     for (size_t k = 0; k < n && rc == PS_OK; ++k) {
-        rc = enqueue_rx(h, cur, 1 - cur, mx, 1 - mx, k == 0 ? pend0 : eps, trigs[k], h->cap_stream, false);
+        rc = enqueue_rx(h, cur, 1 - cur, mx, 1 - mx, k == 0 ? pend0 : eps, trigs[k], h->cap_stream, false, true);
         cur = 1 - cur;
         mx = 1 - mx;
     }
@@ -733,6 +769,7 @@ int merge_gen_runs(ps_handle* h, int b, int bits, int* result) {
     size_t slot;
     rc = ev_begin(h, 2, &slot);
     if (rc) return rc;
+    LB_RESERVE(h, 1);
     HIP_TRY(launch_sort_pass(a, 8, h->dtype, h->LP, h->stream, h->grid));
     rc = ev_end(h, slot);
     if (rc) return rc;
@@ -924,6 +961,7 @@ int sort_by_rank_z(ps_handle* h, int b, int* result, bool full_key = false, bool
         size_t slot;
         rc = ev_begin(h, 2, &slot);
         if (rc) return rc;
+        LB_RESERVE(h, 1);
         HIP_TRY(launch_sort_pass(a, ipt, h->dtype, h->LP, h->stream, h->grid));
         rc = ev_end(h, slot);
         if (rc) return rc;
@@ -969,6 +1007,45 @@ int materialize(ps_handle* h) {
     return check_no_error(h, "truncation");
 }
 
+// ---------------------------------------------------------------- histogram
+int check_histogram_args(ps_handle* h, int lane, const double* edges, int n_bins, uint64_t* counts) {
+    if (!h || !edges || !counts) return fail(PS_ERR_INVALID, "NULL argument");
+    if (h->broken) return fail(PS_ERR_DEVICE, "handle is no longer usable");
+    if (lane < 0 || lane >= h->L) return fail(PS_ERR_INVALID, "lane %d out of range", lane);
+    if (n_bins < 1 || n_bins > kHistMaxBins) return fail(PS_ERR_INVALID, "n_bins must be in 1..%d", kHistMaxBins);
+    for (int k = 0; k <= n_bins; ++k) {
+        if (!std::isfinite(edges[k])) return fail(PS_ERR_NONFINITE, "edge %d is not finite", k);
+        if (k > 0 && !(edges[k] > edges[k - 1])) return fail(PS_ERR_INVALID, "edges must increase");
+    }
+    return PS_OK;
+}
+
+// Counts of the current operator into host counts[n_bins + 2], with device
+// memory dE (n_bins + 1 doubles) and dC (n_bins + 2 words) supplied by the
+// caller.  A pending truncation is applied inside the counting kernel.
+int run_histogram(ps_handle* h, int lane, const double* edges, int n_bins, int is_signed, uint64_t* counts,
+                  double* dE, uint64_t* dC) {
+    HistArgs a{};
+    a.ctrl = h->ctrl;
+    a.buf = h->cur;
+    a.mx = h->mx;
+    a.C = h->buf[h->cur].C;
+    a.cap = h->cap;
+    a.lane = lane;
+    a.nbins = n_bins;
+    a.is_signed = is_signed ? 1 : 0;
+    a.eps_pend = h->pend;
+    a.edges = dE;
+    a.counts = dC;
+    hipError_t e = hipMemcpyAsync(dE, edges, size_t(n_bins + 1) * 8, hipMemcpyHostToDevice, h->stream);
+    if (e == hipSuccess) e = launch_fill_u64(dC, 0, size_t(n_bins + 2), h->stream);
+    if (e == hipSuccess) e = launch_histogram(a, h->dtype, h->LP, h->stream, h->grid);
+    if (e == hipSuccess) e = hipMemcpyAsync(counts, dC, size_t(n_bins + 2) * 8, hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return fail(PS_ERR_HIP, "histogram: %s", hipGetErrorString(e));
+    return PS_OK;
+}
+
 }  // namespace
 
 // ================================================================ C ABI
@@ -1007,6 +1084,7 @@ int pauli_sum_create(int n_qubits, int n_lanes, int dtype, size_t capacity, cons
     {
         int dev = 0, cus = 0;
         (void)hipGetDevice(&dev);
+        h->dev = dev;
         if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
             h->grid = cus * 4;
     }
@@ -1436,13 +1514,41 @@ int pauli_sum_truncate(ps_handle* h, double rel_eps, int trunc_mode) {
 int expectation_z(ps_handle* h, double* out) {
     if (!h || !out) return fail(PS_ERR_INVALID, "NULL argument");
     if (h->broken) return fail(PS_ERR_DEVICE, "handle is no longer usable");
-    int rc = materialize(h);
-    if (rc) return rc;
-    HIP_TRY(launch_reduce(h->ctrl, h->cur, h->buf[h->cur].X, h->buf[h->cur].C, h->cap, 0, h->partial, h->red_out,
-                          h->dtype, h->LP, h->L, h->stream));
+    int src = h->cur;
+    if (h->pend > 0.0) {
+        // Pending truncation: only the x == 0 prefix is read.  Its surviving
+        // strings are compacted, in order, into the front of the spare state
+        // buffer, which then holds exactly the prefix a full truncation pass
+        // would have produced; the operator itself stays as stored.
+        HIP_TRY(launch_prefix_len(h->ctrl, h->cur, h->buf[h->cur].X, h->stream));
+        CompactArgs a{};
+        a.ctrl = h->ctrl;
+        a.in_buf = h->cur;
+        a.out_buf = 1 - h->cur;
+        a.mx_in = h->mx;
+        a.mx_out = 1 - h->mx;
+        a.Xin = h->buf[h->cur].X;
+        a.Zin = h->buf[h->cur].Z;
+        a.Cin = h->buf[h->cur].C;
+        a.Xout = h->buf[1 - h->cur].X;
+        a.Zout = h->buf[1 - h->cur].Z;
+        a.Cout = h->buf[1 - h->cur].C;
+        a.cap = h->cap;
+        a.status = h->status;
+        a.max_tiles = h->max_tiles;
+        a.eps_in = h->pend;
+        a.nq = h->nq;
+        a.prefix_only = 1;
+        LB_RESERVE(h, 1);
+        HIP_TRY(launch_compact(a, h->dtype, h->LP, h->stream, h->grid));
+        src = 1 - h->cur;
+    }
+    HIP_TRY(launch_reduce(h->ctrl, src, h->buf[src].X, h->buf[src].C, h->cap, 0, -1.0, h->mx, h->partial,
+                          h->red_out, h->dtype, h->LP, h->stream));
     double tmp[kMaxLanes];
     HIP_TRY(hipMemcpyAsync(tmp, h->red_out, h->LP * sizeof(double), hipMemcpyDeviceToHost, h->stream));
-    HIP_TRY(hipStreamSynchronize(h->stream));
+    int rc = check_no_error(h, "expectation");
+    if (rc) return rc;
     for (int a = 0; a < h->L; ++a) out[a] = tmp[a];
     return PS_OK;
 }
@@ -1450,13 +1556,13 @@ int expectation_z(ps_handle* h, double* out) {
 int pauli_sum_norm2(ps_handle* h, double* out) {
     if (!h || !out) return fail(PS_ERR_INVALID, "NULL argument");
     if (h->broken) return fail(PS_ERR_DEVICE, "handle is no longer usable");
-    int rc = materialize(h);
-    if (rc) return rc;
-    HIP_TRY(launch_reduce(h->ctrl, h->cur, h->buf[h->cur].X, h->buf[h->cur].C, h->cap, 1, h->partial, h->red_out,
-                          h->dtype, h->LP, h->L, h->stream));
+    // one read of the coefficients; a pending truncation is applied as they are summed
+    HIP_TRY(launch_reduce(h->ctrl, h->cur, h->buf[h->cur].X, h->buf[h->cur].C, h->cap, 1, h->pend, h->mx,
+                          h->partial, h->red_out, h->dtype, h->LP, h->stream));
     double tmp[kMaxLanes];
     HIP_TRY(hipMemcpyAsync(tmp, h->red_out, h->LP * sizeof(double), hipMemcpyDeviceToHost, h->stream));
-    HIP_TRY(hipStreamSynchronize(h->stream));
+    int rc = check_no_error(h, "norm");
+    if (rc) return rc;
     for (int a = 0; a < h->L; ++a) out[a] = tmp[a];
     return PS_OK;
 }
@@ -1593,50 +1699,20 @@ int pauli_sum_stats(ps_handle* h, ps_stats* out, int reset) {
 }
 
 int pauli_sum_histogram(ps_handle* h, int lane, const double* edges, int n_bins, int is_signed, uint64_t* counts) {
-    if (!h || !edges || !counts) return fail(PS_ERR_INVALID, "NULL argument");
-    if (h->broken) return fail(PS_ERR_DEVICE, "handle is no longer usable");
-    if (lane < 0 || lane >= h->L) return fail(PS_ERR_INVALID, "lane %d out of range", lane);
-    if (n_bins < 1 || n_bins > kHistMaxBins) return fail(PS_ERR_INVALID, "n_bins must be in 1..%d", kHistMaxBins);
-    for (int k = 0; k <= n_bins; ++k) {
-        if (!std::isfinite(edges[k])) return fail(PS_ERR_NONFINITE, "edge %d is not finite", k);
-        if (k > 0 && !(edges[k] > edges[k - 1])) return fail(PS_ERR_INVALID, "edges must increase");
-    }
-    int rc = materialize(h);
+    int rc = check_histogram_args(h, lane, edges, n_bins, counts);
     if (rc) return rc;
-    Ctrl c;
-    rc = read_ctrl(h, &c);
-    if (rc) return rc;
-    double M;
-    std::memcpy(&M, &c.maxbits[h->mx][lane], 8);
-    std::vector<double> t(n_bins + 1);
-    for (int k = 0; k <= n_bins; ++k) t[k] = M * edges[k];
-    double* dT = nullptr;
+    double* dE = nullptr;
     uint64_t* dC = nullptr;
-    if (hipMalloc(reinterpret_cast<void**>(&dT), t.size() * 8) != hipSuccess ||
-        hipMalloc(reinterpret_cast<void**>(&dC), (n_bins + 2) * 8) != hipSuccess) {
+    if (hipMalloc(reinterpret_cast<void**>(&dE), size_t(n_bins + 1) * 8) != hipSuccess ||
+        hipMalloc(reinterpret_cast<void**>(&dC), size_t(n_bins + 2) * 8) != hipSuccess) {
         (void)hipGetLastError();
-        if (dT) (void)hipFree(dT);
+        if (dE) (void)hipFree(dE);
         return fail(PS_ERR_CAPACITY, "hipMalloc failed for the histogram");
     }
-    HistArgs a{};
-    a.ctrl = h->ctrl;
-    a.buf = h->cur;
-    a.C = h->buf[h->cur].C;
-    a.cap = h->cap;
-    a.lane = lane;
-    a.nbins = n_bins;
-    a.is_signed = is_signed ? 1 : 0;
-    a.thresholds = dT;
-    a.counts = dC;
-    hipError_t e = hipMemcpyAsync(dT, t.data(), t.size() * 8, hipMemcpyHostToDevice, h->stream);
-    if (e == hipSuccess) e = hipMemsetAsync(dC, 0, (n_bins + 2) * 8, h->stream);
-    if (e == hipSuccess) e = launch_histogram(a, h->dtype, h->LP, h->stream, h->grid);
-    if (e == hipSuccess) e = hipMemcpyAsync(counts, dC, (n_bins + 2) * 8, hipMemcpyDeviceToHost, h->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
-    (void)hipFree(dT);
+    rc = run_histogram(h, lane, edges, n_bins, is_signed, counts, dE, dC);
+    (void)hipFree(dE);
     (void)hipFree(dC);
-    if (e != hipSuccess) return fail(PS_ERR_HIP, "histogram: %s", hipGetErrorString(e));
-    return PS_OK;
+    return rc;
 }
 
 int pauli_sum_set_sort_config(ps_handle* h, int digit_bits, int items_per_thread) {
@@ -1653,6 +1729,28 @@ int pauli_sum_set_sort_config(ps_handle* h, int digit_bits, int items_per_thread
     }
     return fail(PS_ERR_INVALID, "no radix-sort configuration with %d-bit digits and %d items per thread", digit_bits,
                 items_per_thread);
+}
+
+int pauli_sum_set_lookback_epoch(ps_handle* h, uint32_t epoch) {
+    if (!h) return fail(PS_ERR_INVALID, "NULL argument");
+    if (h->broken) return fail(PS_ERR_DEVICE, "handle is no longer usable");
+    if (epoch < 1 || epoch >= kEpochLimit)
+        return fail(PS_ERR_INVALID, "epoch must be in 1..%llu", static_cast<unsigned long long>(kEpochLimit - 1));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    HIP_TRY(launch_fill_u64(h->status, 0ull, h->status_words, h->stream));
+    HIP_TRY(hipMemcpyAsync(&h->ctrl->epoch, &epoch, sizeof epoch, hipMemcpyHostToDevice, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    h->lb_count = epoch - 1;
+    return PS_OK;
+}
+
+int pauli_sum_lookback_epoch(ps_handle* h, uint32_t* epoch) {
+    if (!h || !epoch) return fail(PS_ERR_INVALID, "NULL argument");
+    Ctrl c;
+    int rc = read_ctrl(h, &c);
+    if (rc) return rc;
+    *epoch = c.epoch;
+    return PS_OK;
 }
 
 int pauli_sum_set_graphs(ps_handle* h, int enable) {

@@ -5,21 +5,35 @@
 namespace orqa {
 
 // Counts of v = c (signed) or |c| over bins [t_k, t_(k+1)), the last one
-// closed, with t_k = M * edge_k supplied by the host (M = max |c| of the
-// lane).  counts[nb] takes values below t_0, counts[nb + 1] values above t_nb.
+// closed, with t_k = M * edge_k (M = max |c| of the lane).  counts[nb] takes
+// values below t_0, counts[nb + 1] values above t_nb.  Strings that the
+// pending truncation of the operator drops are skipped (the max is that of
+// the untruncated operator, which truncation never lowers: the largest
+// string survives any eps0 < 1, and with eps0 >= 1 nothing is counted).
 template <typename CT, int LP>
 __global__ __launch_bounds__(kThreads) void k_histogram(HistArgs A) {
     __shared__ double sT[kHistMaxBins + 1];
     __shared__ uint32_t sC[kHistMaxBins + 2];
+    __shared__ double sThr[LP];
     const CT* __restrict__ C = static_cast<const CT*>(A.C);
     const int nb = A.nbins;
-    for (int k = threadIdx.x; k <= nb; k += kThreads) sT[k] = A.thresholds[k];
+    const double M = bits_to_d(A.ctrl->maxbits[A.mx][A.lane]);
+    for (int k = threadIdx.x; k <= nb; k += kThreads) sT[k] = M * A.edges[k];
     for (int k = threadIdx.x; k < nb + 2; k += kThreads) sC[k] = 0;
+    const bool filt = A.eps_pend > 0.0;
+    if (threadIdx.x < LP) sThr[threadIdx.x] = filt ? A.eps_pend * bits_to_d(A.ctrl->maxbits[A.mx][threadIdx.x]) : -1.0;
     __syncthreads();
     const uint64_t nf = A.ctrl->nf[A.buf];
     const uint64_t n = nf + A.ctrl->nb[A.buf];
     for (uint64_t i = blockIdx.x * uint64_t(kThreads) + threadIdx.x; i < n; i += uint64_t(gridDim.x) * kThreads) {
-        const double c = static_cast<double>(C[vphys(i, nf, A.cap) * LP + A.lane]);
+        const CT* row = C + vphys(i, nf, A.cap) * LP;
+        if (filt) {
+            bool keep = false;
+#pragma unroll
+            for (int a = 0; a < LP; ++a) keep |= absd(row[a]) > sThr[a];
+            if (!keep) continue;
+        }
+        const double c = static_cast<double>(row[A.lane]);
         const double v = A.is_signed ? c : absd(c);
         int slot;
         if (v < sT[0]) {

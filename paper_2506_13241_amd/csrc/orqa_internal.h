@@ -122,6 +122,12 @@ struct CompactArgs {
     int gate_count;      // gates this pass stands for (measurement counters)
     const float* gscore;  // learned truncation: log10 predicted weight per input string, or null
     double eps_learned;
+    // prefix_only: compact only the first ctrl->prefix_len strings of the
+    // input (the x == 0 prefix) for a readout, with no other effect on the
+    // handle: no maxima, counters or sizes of the operator are touched; the
+    // result's length replaces ctrl->prefix_len and becomes the size of the
+    // output buffer
+    int prefix_only;
 };
 
 // A radix-sort key is read as one integer whose 64-bit words, least
@@ -234,16 +240,20 @@ hipError_t launch_merge_pairs(const MergeArgs& a, int dtype, int lp, hipStream_t
 hipError_t launch_gen_branch(const GenArgs& a, const GateTrig& g, int dtype, int lp, hipStream_t s, int grid);
 hipError_t launch_gen_reduce(const GenArgs& a, int dtype, int lp, hipStream_t s, int grid);
 
-// Coefficient histogram (Pauli-string density, Appendix D).
+// Coefficient histogram (Pauli-string density, Appendix D).  Thresholds are
+// formed on the device as M * edge_k (binary64 products, M = the lane's max
+// |c| in ctrl->maxbits[mx]); strings a pending truncation would drop
+// (|c| <= eps_pend * max |c| in every lane) are not counted.
 constexpr int kHistMaxBins = 4096;
 struct HistArgs {
     const Ctrl* ctrl;
-    int buf;
+    int buf, mx;
     const void* C;
     uint64_t cap;
     int lane, nbins, is_signed;
-    const double* thresholds;  // nbins + 1, increasing
-    uint64_t* counts;          // nbins + 2
+    double eps_pend;       // pending truncation of the operator (<= 0: none)
+    const double* edges;   // nbins + 1, increasing (device)
+    uint64_t* counts;      // nbins + 2 (device, zeroed by the caller)
 };
 hipError_t launch_histogram(const HistArgs& a, int dtype, int lp, hipStream_t s, int grid);
 
@@ -272,8 +282,13 @@ hipError_t launch_histogram(const HistArgs& a, int dtype, int lp, hipStream_t s,
         }                                                \
     } while (0)
 
+// mode 0: <Z> over the x == 0 prefix of buffer buf (no pending truncation:
+// compact the prefix first); mode 1: sum of c^2 over the buffer, skipping the
+// strings a pending truncation eps_pend (max slot mx) drops.
 hipError_t launch_reduce(Ctrl* ctrl, int buf, const ulonglong2* X, const void* C, uint64_t cap, int mode,
-                         double* partial, double* out, int dtype, int lp, int lanes, hipStream_t s);
+                         double eps_pend, int mx, double* partial, double* out, int dtype, int lp, hipStream_t s);
 hipError_t launch_fill_u64(uint64_t* p, uint64_t v, size_t n, hipStream_t s);
+// Length of the x == 0 prefix of buffer buf into ctrl->prefix_len.
+hipError_t launch_prefix_len(Ctrl* ctrl, int buf, const ulonglong2* X, hipStream_t s);
 
 }  // namespace orqa

@@ -497,7 +497,7 @@ __global__ __launch_bounds__(kThreads) void k_compact(CompactArgs A) {
     const int tid = threadIdx.x, wave = tid >> 6;
     const bool skip = ctrl->err != 0u;
     const uint64_t nf = ctrl->nf[A.in_buf];
-    const uint64_t n = nf + ctrl->nb[A.in_buf];
+    const uint64_t n = A.prefix_only ? ctrl->prefix_len : nf + ctrl->nb[A.in_buf];
     const uint64_t ntiles = skip ? 0 : (n + kCompactTile - 1) / kCompactTile;
     const uint32_t ep = ctrl->epoch;
     const bool filt = A.eps_in > 0.0;
@@ -577,7 +577,7 @@ __global__ __launch_bounds__(kThreads) void k_compact(CompactArgs A) {
         if (tile == ntiles - 1 && tid == 0) {
             ctrl->nf[A.out_buf] = sBase[0] + (totPacked & 0xFFFFu);
             ctrl->nb[A.out_buf] = 0;
-            ctrl->nranks = sBase[1] + (totPacked >> 16);
+            if (!A.prefix_only) ctrl->nranks = sBase[1] + (totPacked >> 16);
         }
 #pragma unroll
         for (int k = 0; k < kCompactIPT; ++k) {
@@ -615,15 +615,23 @@ __global__ __launch_bounds__(kThreads) void k_compact(CompactArgs A) {
         }
         __syncthreads();
     }
+    if (!A.prefix_only) {
 #pragma unroll
-    for (int a = 0; a < LP; ++a) {
-        const double mx = wave_max_d(vmax[a]);
-        if (lane_id() == 0 && mx > 0.0)
-            atomicMax(reinterpret_cast<unsigned long long*>(&ctrl->maxbits[A.mx_out][a]),
-                      static_cast<unsigned long long>(d_to_bits(mx)));
+        for (int a = 0; a < LP; ++a) {
+            const double mx = wave_max_d(vmax[a]);
+            if (lane_id() == 0 && mx > 0.0)
+                atomicMax(reinterpret_cast<unsigned long long*>(&ctrl->maxbits[A.mx_out][a]),
+                          static_cast<unsigned long long>(d_to_bits(mx)));
+        }
     }
     if (finish_launch(ctrl)) {
-        if (__hip_atomic_load(&ctrl->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u) {
+        if (A.prefix_only) {
+            if (ntiles == 0) {
+                ctrl->nf[A.out_buf] = 0;
+                ctrl->nb[A.out_buf] = 0;
+            }
+            ctrl->prefix_len = __hip_atomic_load(&ctrl->nf[A.out_buf], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        } else if (__hip_atomic_load(&ctrl->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u) {
             for (int a = 0; a < kMaxLanes; ++a) ctrl->maxbits[A.mx_in][a] = 0ull;
             if (ntiles == 0) {
                 ctrl->nf[A.out_buf] = 0;
@@ -783,11 +791,18 @@ __global__ void k_prefix_len(Ctrl* ctrl, int buf, const ulonglong2* __restrict__
     ctrl->prefix_len = lo;
 }
 
+// eps_pend > 0 (mode 1 only): strings the pending truncation drops (|c| <=
+// eps_pend * max |c| in every lane, max from slot mx) contribute nothing.
 template <typename CT, int LP>
 __global__ __launch_bounds__(kThreads) void k_reduce_partial(const Ctrl* __restrict__ ctrl, int buf,
                                                              const CT* __restrict__ C, uint64_t cap, int mode,
+                                                             double eps_pend, int mx,
                                                              double* __restrict__ partial) {
     __shared__ double sAcc[4][LP];
+    __shared__ double sThr[LP];
+    const bool filt = mode == 1 && eps_pend > 0.0;
+    if (threadIdx.x < LP) sThr[threadIdx.x] = filt ? eps_pend * bits_to_d(ctrl->maxbits[mx][threadIdx.x]) : -1.0;
+    __syncthreads();
     const uint64_t nf = ctrl->nf[buf];
     const uint64_t len = (mode == 0) ? ctrl->prefix_len : nf + ctrl->nb[buf];
     const uint64_t chunk = (len + gridDim.x - 1) / gridDim.x;
@@ -798,6 +813,7 @@ __global__ __launch_bounds__(kThreads) void k_reduce_partial(const Ctrl* __restr
     for (int a = 0; a < LP; ++a) acc[a] = 0.0;
     for (uint64_t i = b0 + threadIdx.x; i < b1; i += kThreads) {
         const uint64_t p = vphys(i, nf, cap);
+        if (filt && !keep_row<CT, LP>(C + p * LP, sThr)) continue;
 #pragma unroll
         for (int a = 0; a < LP; ++a) {
             const double v = static_cast<double>(C[p * LP + a]);
@@ -1002,15 +1018,19 @@ hipError_t launch_sort_pass(const SortPassArgs& a, int ipt, int dtype, int lp, h
 }
 
 hipError_t launch_reduce(Ctrl* ctrl, int buf, const ulonglong2* X, const void* C, uint64_t cap, int mode,
-                         double* partial, double* out, int dtype, int lp, int lanes, hipStream_t s) {
-    (void)lanes;
+                         double eps_pend, int mx, double* partial, double* out, int dtype, int lp, hipStream_t s) {
     if (mode == 0) k_prefix_len<<<1, 64, 0, s>>>(ctrl, buf, X, cap);
 #define L_RD(T, L)                                                                                    \
     k_reduce_partial<T, L><<<dim3(kReduceBlocks), dim3(kThreads), 0, s>>>(ctrl, buf, static_cast<const T*>(C), \
-                                                                          cap, mode, partial);        \
+                                                                          cap, mode, eps_pend, mx, partial); \
     k_reduce_final<L><<<1, 64, 0, s>>>(partial, kReduceBlocks, out)
     ORQA_DISPATCH(dtype, lp, L_RD);
 #undef L_RD
+    return hipGetLastError();
+}
+
+hipError_t launch_prefix_len(Ctrl* ctrl, int buf, const ulonglong2* X, hipStream_t s) {
+    k_prefix_len<<<1, 64, 0, s>>>(ctrl, buf, X, 0);
     return hipGetLastError();
 }
 

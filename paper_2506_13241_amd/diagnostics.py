@@ -44,6 +44,17 @@ def log_density_edges(eps: float, bins: int) -> np.ndarray:
     return np.logspace(math.log10(eps) - 1.0, 0.0, bins + 1)
 
 
+def density(op, n_bins: int = 200, signed: bool = True, lane: int = 0):
+    """D_t(x) of Appendix D from the library's counts: the histogram of
+    x = O_I / max|O_I| over n_bins uniform bins on [-1, 1] (signed) or [0, 1],
+    normalized to integrate to 1; returns (bin centres, density)."""
+    edges = np.linspace(-1.0 if signed else 0.0, 1.0, n_bins + 1)
+    cnt = op.histogram(edges, signed, lane)[:n_bins].astype(np.float64)
+    width = edges[1] - edges[0]
+    total = cnt.sum()
+    return 0.5 * (edges[1:] + edges[:-1]), (cnt / (total * width) if total else cnt)
+
+
 def run_curves(lat, obs, theta_x, eps, steps, theta_zz=-math.pi / 2, dtype=0, density_bins=0, emit=print):
     zz, rx = w.kicked_ising_step(lat, theta_x, theta_zz)
     op = PauliSum(lat.n, *w.single_pauli_term(lat.n, {obs: "Z"}), dtype=dtype)

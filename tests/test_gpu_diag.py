@@ -35,7 +35,8 @@ def test_density_127q_kicked_ising_counts_equal_oracle():
         want = density_counts(c, edges, signed)
         say(f"n = {len(c)}, bins {len(edges) - 1} signed={signed}: below/above {got[-2:]}")
         assert np.array_equal(got, want)
-    xg, dg = g.density(100)
+    from paper_2506_13241_amd.diagnostics import density as gpu_density
+    xg, dg = gpu_density(g, 100)
     xo, do = density(c, 100)
     assert np.array_equal(xg, xo) and np.array_equal(dg, do)
 
