@@ -194,6 +194,21 @@ int pauli_sum_export(ps_handle* h, ps_pauli* keys, void* coeffs, size_t cap, siz
 int pauli_sum_histogram(ps_handle* h, int lane, const double* edges, int n_bins, int is_signed, uint64_t* counts);
 
 /*
+ * pauli_sum_histogram_noalloc -- pauli_sum_histogram for callers that cannot
+ * allocate device memory (code that may run under HIP graph capture set-up,
+ * tight serving loops, harnesses that forbid hipMalloc).  Same arguments,
+ * counts and errors, but the call allocates and frees nothing: its edges and
+ * counters (at most 4096 bins, 64 KiB and a bit) live in one fixed device
+ * array of the library, one copy per GPU, held until the process ends.  The
+ * counters are cleared by every call.  All calls on one GPU share that array:
+ * calls that overlap in time on the same GPU (two host threads, or handles on
+ * two streams) race and may return wrong counts.  n_bins above 4096:
+ * PS_ERR_INVALID.
+ */
+int pauli_sum_histogram_noalloc(ps_handle* h, int lane, const double* edges, int n_bins, int is_signed,
+                                uint64_t* counts);
+
+/*
  * pauli_sum_set_sort_config -- digit width and tile size of the radix sort
  * (the re-sort after a Clifford layer, Eq. (u), when its x-groups are too large
  * for the in-group sort, and the sort of general gates, Eq. update_rule, whose

@@ -27,7 +27,7 @@ EXPORTED_SYMBOLS = (
     "pauli_sum_load_scorer", "pauli_sum_set_timing", "pauli_sum_stats", "ps_last_error",
     "ps_scorer_create", "ps_scorer_destroy", "ps_scorer_set_params", "ps_scorer_get_params", "ps_scorer_set_data",
     "ps_scorer_forward", "ps_scorer_loss_grad", "ps_scorer_adam_step", "pauli_sum_set_graphs",
-    "pauli_sum_histogram", "pauli_sum_set_sort_config",
+    "pauli_sum_histogram", "pauli_sum_set_sort_config", "pauli_sum_histogram_noalloc",
     "pauli_sum_set_lookback_epoch", "pauli_sum_lookback_epoch",
 )
 N_SCORER_PARAMS = 37249
@@ -87,6 +87,7 @@ def load_library(path: str = LIB_PATH):
         "ps_last_error": (ctypes.c_char_p, []),
         "pauli_sum_set_graphs": (I, [P, I]),
         "pauli_sum_histogram": (I, [P, I, P, I, I, P]),
+        "pauli_sum_histogram_noalloc": (I, [P, I, P, I, I, P]),
         "pauli_sum_set_lookback_epoch": (I, [P, ctypes.c_uint32]),
         "pauli_sum_lookback_epoch": (I, [P, ctypes.POINTER(ctypes.c_uint32)]),
         "pauli_sum_set_sort_config": (I, [P, I, I]),
@@ -227,12 +228,14 @@ class PauliSum:
         t, c = self.export()
         return {tuple(int(v) for v in row): c[i].copy() for i, row in enumerate(t)}
 
-    def histogram(self, edges, signed: bool = True, lane: int = 0) -> np.ndarray:
+    def histogram(self, edges, signed: bool = True, lane: int = 0, noalloc: bool = False) -> np.ndarray:
         """Counts over the bins given by `edges` (relative to max|c|), then the
-        counts below and above the range (Pauli-string density, Appendix D)."""
+        counts below and above the range (Pauli-string density, Appendix D).
+        noalloc: use pauli_sum_histogram_noalloc (no device allocation)."""
         e = np.ascontiguousarray(edges, dtype=np.float64)
         out = np.zeros(e.size + 1, dtype=np.uint64)
-        _check(_lib.pauli_sum_histogram(self._h, lane, _ptr(e), e.size - 1, int(signed), _ptr(out)))
+        f = _lib.pauli_sum_histogram_noalloc if noalloc else _lib.pauli_sum_histogram
+        _check(f(self._h, lane, _ptr(e), e.size - 1, int(signed), _ptr(out)))
         return out
 
     def set_lookback_epoch(self, epoch: int):
@@ -352,6 +355,10 @@ def pauli_sum_export(ps: PauliSum):
 
 def pauli_sum_histogram(ps: PauliSum, edges, signed=True, lane=0):
     return ps.histogram(edges, signed, lane)
+
+
+def pauli_sum_histogram_noalloc(ps: PauliSum, edges, signed=True, lane=0):
+    return ps.histogram(edges, signed, lane, noalloc=True)
 
 
 def pauli_sum_set_lookback_epoch(ps: PauliSum, epoch: int):

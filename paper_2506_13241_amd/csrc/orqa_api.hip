@@ -5,6 +5,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1046,6 +1047,39 @@ int run_histogram(ps_handle* h, int lane, const double* edges, int n_bins, int i
     return PS_OK;
 }
 
+// ---------------------------------------------------------------- fixed scratch
+// Device memory of pauli_sum_histogram_noalloc: the bin edges (kHistMaxBins + 1
+// doubles) followed by the counters (kHistMaxBins + 2 words), 64 KiB and a bit
+// in one fixed array.  Every GPU the library runs on holds its own copy until
+// the process ends.  In host code `scratch` names a host-side stand-in, not
+// device memory: its device address is looked up once per device with
+// hipGetSymbolAddress (with that device current) and only that address is
+// handed to kernels and copies.
+constexpr size_t kScratchCountsAt = kHistMaxBins + 1;
+constexpr size_t kScratchWords = kScratchCountsAt + kHistMaxBins + 2;
+static __device__ __align__(256) uint64_t scratch[kScratchWords];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on device dev, which must be current.
+int scratch_address(int dev, void** out) {
+    if (dev < 0 || dev >= kMaxDevices) return fail(PS_ERR_UNSUPPORTED, "device %d beyond the scratch table", dev);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            (void)hipGetLastError();
+            return fail(PS_ERR_HIP, "hipGetSymbolAddress(scratch) on device %d: %s", dev, hipGetErrorString(e));
+        }
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return PS_OK;
+}
+
 }  // namespace
 
 // ================================================================ C ABI
@@ -1712,6 +1746,24 @@ int pauli_sum_histogram(ps_handle* h, int lane, const double* edges, int n_bins,
     rc = run_histogram(h, lane, edges, n_bins, is_signed, counts, dE, dC);
     (void)hipFree(dE);
     (void)hipFree(dC);
+    return rc;
+}
+
+int pauli_sum_histogram_noalloc(ps_handle* h, int lane, const double* edges, int n_bins, int is_signed,
+                                uint64_t* counts) {
+    int rc = check_histogram_args(h, lane, edges, n_bins, counts);
+    if (rc) return rc;
+    int prev = -1;
+    if (hipGetDevice(&prev) != hipSuccess) return fail(PS_ERR_HIP, "hipGetDevice failed");
+    if (prev != h->dev) HIP_TRY(hipSetDevice(h->dev));
+    void* base = nullptr;
+    rc = scratch_address(h->dev, &base);
+    if (!rc) {
+        double* dE = static_cast<double*>(base);
+        uint64_t* dC = static_cast<uint64_t*>(base) + kScratchCountsAt;
+        rc = run_histogram(h, lane, edges, n_bins, is_signed, counts, dE, dC);
+    }
+    if (prev != h->dev) (void)hipSetDevice(prev);
     return rc;
 }
 
