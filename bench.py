@@ -15,6 +15,12 @@ timed step of the number of strings the gate acts on, divided by the wall time
 for the dominant kernel, the RX merge pass: algorithmic bytes per launch =
 (strings read + strings written) x 40 B, divided by its mean launch time from
 HIP events on the library's stream.
+
+--lanes theta32 | obs16 times the batched forms instead: 32 values of theta_h
+in [0, pi/2] carried as binary32 coefficient lanes of one operator, or 16
+random weight-1/2 Z observables (seed 20250616) at theta_h = 0.8; their line
+also reports string x lane updates per second, and the roofline bytes per
+string are 32 + 4 x 32 (key words + padded lanes).
 """
 
 from __future__ import annotations
@@ -30,6 +36,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
+# (eps0, warmup steps, timed steps, dtype) of the batched forms at one GPU
+LANES_ONE_GPU = {"theta32": (1e-3, 13, 2, "f32"), "obs16": (1e-3, 13, 2, "f32")}
 
 
 def log(*a):
@@ -48,21 +56,45 @@ def kernel_source_sha():
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
-    """HBM bytes per RX merge launch from the committed rocprofv3 summary, or
-    None when the kernel source changed since those counters were taken."""
+def workload_key(args) -> str:
+    """The configuration a committed counter figure belongs to."""
+    return (f"lanes={args.lanes} dtype={args.dtype} eps={args.eps:g} theta={args.theta:g} "
+            f"theta_zz={args.theta_zz:.6f} trunc={args.trunc} steps={args.warmup + 1}-{args.warmup + args.steps}")
+
+
+def read_profile_fields(path):
+    fields = {}
+    for line in open(path):
+        if ":" in line and not line.startswith(("#", " ", "|", "-")):
+            k, v = line.split(":", 1)
+            fields[k.strip()] = v.strip()
+    return fields
+
+
+def measured_traffic(key):
+    """HBM bytes per RX merge launch from a committed rocprofv3 summary taken
+    on this workload key (configuration and step window) with the current
+    kernel sources, as (bytes, algorithmic bytes of those launches, file);
+    (None, None, None) when no summary matches."""
     import glob
-    import hashlib
     sha = kernel_source_sha()
-    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "k_rx_merge__*fp64.md"))):
-        fields = {}
-        for line in open(path):
-            if ":" in line and not line.startswith(("#", " ", "|", "-")):
-                k, v = line.split(":", 1)
-                fields[k.strip()] = v.strip()
-        if fields.get("kernel_source_sha256_16") == sha and "traffic_bytes_per_launch" in fields:
-            return float(fields["traffic_bytes_per_launch"]), os.path.basename(path)
-    return None, None
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "k_rx_merge__*.md"))):
+        f = read_profile_fields(path)
+        if f.get("kernel_source_sha256_16") == sha and f.get("workload_key") == key and \
+                "traffic_bytes_per_launch" in f and "algorithmic_bytes_per_launch" in f:
+            return float(f["traffic_bytes_per_launch"]), float(f["algorithmic_bytes_per_launch"]), \
+                os.path.basename(path)
+    return None, None, None
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def cpu_baseline(theta, eps0, budget_s, theta_zz=-math.pi / 2):
@@ -98,6 +130,7 @@ def cpu_baseline(theta, eps0, budget_s, theta_zz=-math.pi / 2):
         "value": o.updates() / dt,
         "unit": "string-updates/s",
         "cores": 1,
+        "cpu_model": cpu_model(),
         "kind": "oracle",
         "sample": f"Trotter steps 1-{steps_done} of the same workload plus {part} gates of step "
                   f"{steps_done + 1} ({n_gates} gates, {dt:.1f} s, {o.updates():.3g} string-updates)",
@@ -107,13 +140,16 @@ def cpu_baseline(theta, eps0, budget_s, theta_zz=-math.pi / 2):
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2)
-    ap.add_argument("--warmup", type=int, default=18)
+    ap.add_argument("--steps", type=int, default=None, help="timed Trotter steps (default 2)")
+    ap.add_argument("--warmup", type=int, default=None,
+                    help="untimed Trotter steps before them (default 18; with --lanes, the one-GPU form's)")
+    ap.add_argument("--lanes", choices=["none", "theta32", "obs16"], default="none",
+                    help="batched forms: 32 theta_h lanes, or 16 observable lanes (binary32 by default)")
     ap.add_argument("--theta", type=float, default=0.8)
     ap.add_argument("--theta-zz", type=float, default=-math.pi / 2,
                     help="RZZ angle; away from multiples of pi/2 every RZZ takes the general-rotation path")
-    ap.add_argument("--eps", type=float, default=1e-4)
-    ap.add_argument("--dtype", choices=["f64", "f32"], default="f64")
+    ap.add_argument("--eps", type=float, default=None, help="eps0 (default 1e-4; with --lanes, the one-GPU form's)")
+    ap.add_argument("--dtype", choices=["f64", "f32"], default=None, help="default f64; f32 with --lanes")
     ap.add_argument("--reference-f64", action="store_true",
                     help="after the run, repeat it untimed in binary64 (magnitude rule) and report |delta <Z62>| per step")
     ap.add_argument("--trunc", choices=["magnitude", "learned"], default="magnitude",
@@ -124,6 +160,18 @@ def main():
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES (calibrates rocprofv3 byte counters)")
     args = ap.parse_args()
+    # the largest batched forms that fit one GPU (measured: the 15-step runs at
+    # eps0 = 1e-4 outgrow 288 GB at step 6)
+    one_gpu = {"none": (1e-4, 18, 2, "f64"), "theta32": LANES_ONE_GPU["theta32"],
+               "obs16": LANES_ONE_GPU["obs16"]}[args.lanes]
+    if args.eps is None:
+        args.eps = one_gpu[0]
+    if args.warmup is None:
+        args.warmup = one_gpu[1]
+    if args.steps is None:
+        args.steps = one_gpu[2]
+    if args.dtype is None:
+        args.dtype = one_gpu[3]
     if args.copy_probe:
         import torch
         x = torch.empty(args.copy_probe // 4, dtype=torch.float32, device="cuda").fill_(1.0)
@@ -148,14 +196,29 @@ def main():
         sys.exit(2)
 
     import torch
+    import numpy as np
     import paper_2506_13241_amd as P
     import workload as w
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     lat = w.eagle_127()
-    zz, rx = w.kicked_ising_step(lat, args.theta, theta_zz=args.theta_zz)
-    terms, coef = w.single_pauli_term(lat.n, {62: "Z"})
+    lanes = {"none": 1, "theta32": 32, "obs16": 16}[args.lanes]
+    if args.lanes == "theta32":
+        thetas = np.linspace(0.0, math.pi / 2, 32)
+        zz, rx = w.kicked_ising_step(lat, thetas, theta_zz=args.theta_zz, lanes=32)
+        terms, coef = w.single_pauli_term(lat.n, {62: "Z"}, lanes=32)
+        what = "theta_h = 32 values in [0, pi/2] as binary32 lanes, O0=Z62"
+    elif args.lanes == "obs16":
+        obs = w.random_observables(lat.n, 16, 20250616)
+        terms = np.stack([w.pauli_words(lat.n, ob) for ob in obs])
+        coef = np.eye(16)
+        zz, rx = w.kicked_ising_step(lat, args.theta, theta_zz=args.theta_zz, lanes=16)
+        what = f"16 weight-1/2 Z observables (seed 20250616) as lanes, theta_h={args.theta}"
+    else:
+        zz, rx = w.kicked_ising_step(lat, args.theta, theta_zz=args.theta_zz)
+        terms, coef = w.single_pauli_term(lat.n, {62: "Z"})
+        what = f"O0=Z62, theta_h={args.theta}"
     dtype = P.PS_F64 if args.dtype == "f64" else P.PS_F32
     ps = P.PauliSum(lat.n, terms, coef, dtype=dtype, capacity=1 << 22)
     mode = P.PS_TRUNC_MAGNITUDE
@@ -171,9 +234,9 @@ def main():
     t_start = time.perf_counter()
     for s in range(args.warmup):
         ps.apply_rotation_layer(zz, args.eps, mode).apply_rotation_layer(rx, args.eps, mode)
-        ez_all.append(float(ps.expectation_z()[0]))
+        ez_all.append([float(v) for v in ps.expectation_z()])
         if args.verbose:
-            log(f"warmup step {s + 1}: |O|={ps.size()} <Z62>={ez_all[-1]:.12f} t={time.perf_counter() - t_start:.2f}s")
+            log(f"warmup step {s + 1}: |O|={ps.size()} <Z>={ez_all[-1][0]:.12f} t={time.perf_counter() - t_start:.2f}s")
     n_before = ps.size()
     ps.stats(reset=True)
     ps.set_timing(True)
@@ -181,9 +244,9 @@ def main():
     t0 = time.perf_counter()
     for s in range(args.steps):
         ps.apply_rotation_layer(zz, args.eps, mode).apply_rotation_layer(rx, args.eps, mode)
-        ez_all.append(float(ps.expectation_z()[0]))
+        ez_all.append([float(v) for v in ps.expectation_z()])
         if args.verbose:
-            log(f"timed step {args.warmup + s + 1}: <Z62>={ez_all[-1]:.12f} t={time.perf_counter() - t0:.2f}s")
+            log(f"timed step {args.warmup + s + 1}: <Z>={ez_all[-1][0]:.12f} t={time.perf_counter() - t0:.2f}s")
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     st = ps.stats()
@@ -195,6 +258,7 @@ def main():
     rx_bytes = (st["rx_in"] + st["rx_out"]) * bps
     rx_ms_mean = st["rx_ms"] / max(st["rx_launches"], 1)
     achieved = rx_bytes / (st["rx_ms"] * 1e-3) / 1e9 if st["rx_ms"] > 0 else 0.0
+    alg_per_launch = rx_bytes / max(st["rx_launches"], 1)
     roofline = {
         "bound": "hbm",
         "kernel": "k_rx_merge",
@@ -206,16 +270,25 @@ def main():
         "traffic_source": None,
         "launches": int(st["rx_launches"]),
         "mean_launch_ms": round(rx_ms_mean, 4),
-        "algorithmic_bytes_per_launch": round(rx_bytes / max(st["rx_launches"], 1)),
+        "algorithmic_bytes_per_launch": round(alg_per_launch),
+        "bytes_per_string": bps,
     }
-    traffic, tsrc = measured_traffic()
+    key = workload_key(args)
+    traffic, traffic_alg, tsrc = measured_traffic(key)
     if traffic is not None:
-        roofline["traffic"] = traffic
-        roofline["traffic_source"] = tsrc
+        # the counters were taken on this workload key (same launches): their
+        # ratio to the algorithmic bytes is carried over to this run's launches
+        roofline["traffic"] = round(traffic / traffic_alg * alg_per_launch)
+        roofline["traffic_source"] = f"{tsrc}: {traffic:.0f} B per launch against {traffic_alg:.0f} algorithmic"
+    roofline["workload_key"] = key
+    rx_updates = st["rx_in"]
     extra = {
         "strings_before": n_before,
         "strings_after": n_after,
-        "ez_z62_per_step": ez_all,
+        "rx_updates_per_s": rx_updates / dt,
+        "rx_updates_note": "string-updates of the 127 RX gates of each step only (value also counts the 144 "
+                           "RZZ gates, which one fused pass applies)",
+        "ez_per_step": ez_all if lanes > 1 else [e[0] for e in ez_all],
         "ms_rx_merge_total": round(st["rx_ms"], 3),
         "ms_clifford_total": round(st["cliff_ms"], 3),
         "ms_sort_total": round(st["sort_ms"], 3),
@@ -224,6 +297,10 @@ def main():
         "run_merges": int(st["run_merges"]),
         "paper_time_per_gate_ms": round(dt / args.steps / 271 * 1e3, 4),
     }
+    if lanes > 1:
+        extra["lanes"] = lanes
+        extra["string_lane_updates_per_s"] = updates * lanes / dt
+        extra["bytes_per_string_lane"] = bps / lanes
     if st["score_launches"] > 0:
         flop = 2 * (160 * 128 + 128 * 128 + 128) * st["score_in"]
         extra["scorer"] = {
@@ -238,18 +315,18 @@ def main():
         ez_ref = []
         for s in range(args.warmup + args.steps):
             ref.apply_rotation_layer(zz, args.eps).apply_rotation_layer(rx, args.eps)
-            ez_ref.append(float(ref.expectation_z()[0]))
+            ez_ref.append([float(v) for v in ref.expectation_z()])
         ref.close()
-        d = [abs(a - b) for a, b in zip(ez_all, ez_ref)]
-        extra["ez_z62_f64_magnitude"] = ez_ref
+        d = [max(abs(a - b) for a, b in zip(x, y)) for x, y in zip(ez_all, ez_ref)]
+        extra["ez_f64_magnitude"] = ez_ref if lanes > 1 else [e[0] for e in ez_ref]
         extra["dz_vs_f64_per_step"] = d
         extra["dz_vs_f64_max"] = max(d)
     cpu = None
-    if not args.no_cpu_baseline and args.trunc == "magnitude":
+    if not args.no_cpu_baseline and args.trunc == "magnitude" and lanes == 1:
         cpu, ez_cpu = cpu_baseline(args.theta, args.eps, args.cpu_budget, args.theta_zz)
         k = min(len(ez_cpu), len(ez_all))
         if k:
-            extra["dz_vs_oracle_max"] = max(abs(a - b) for a, b in zip(ez_all[:k], ez_cpu[:k]))
+            extra["dz_vs_oracle_max"] = max(abs(a[0] - b) for a, b in zip(ez_all[:k], ez_cpu[:k]))
             extra["dz_vs_oracle_steps"] = k
     line = {
         "metric": "Pauli-string updates/s (and s per Trotter step) at 127q",
@@ -265,13 +342,14 @@ def main():
         "dtype": args.dtype,
         "data": "synthetic: deterministic kicked-Ising circuit, no dataset",
         "config": {
-            "workload": f"kicked Ising 127q heavy-hex, O0=Z62, theta_h={args.theta}, "
+            "workload": f"kicked Ising 127q heavy-hex, {what}, "
                         + ("theta_zz=-pi/2, " if abs(args.theta_zz + math.pi / 2) < 1e-15 else f"theta_zz={args.theta_zz}, ")
                         + f"eps0={args.eps} per gate"
                         + (" + learned truncation once per step" if args.trunc == "learned" else "")
                         + f", Trotter steps {args.warmup + 1}-{args.warmup + args.steps}",
             "qubits": 127,
             "gates_per_step": 271,
+            "lanes": lanes,
         },
         "roofline": roofline,
         "cpu_baseline": cpu,

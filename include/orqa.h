@@ -132,15 +132,26 @@ int expectation_z(ps_handle* h, double* out);
 /* pauli_sum_size -- number of strings held (|O|, the effective complexity, Methods). */
 int pauli_sum_size(ps_handle* h, size_t* n);
 
-/* pauli_sum_norm2 -- sum_I O_I,a^2 per lane, binary64 (host out[n_lanes]). */
+/*
+ * pauli_sum_norm2 -- sum_I O_I,a^2 per lane, binary64 (host out[n_lanes]).
+ * With the coefficients of Eq. define_O being the normalised traces on the
+ * left of Eq. update_rule, this is Tr[O^2] / 2^n.  Every gate maps each pair
+ * {I, I xor J} by a rotation (Eq. update_rule), so the value is conserved
+ * without truncation; truncation (Eq. truncation1) lowers it by the squares
+ * it drops (the value is that of the operator after the last gate's
+ * truncation).
+ */
 int pauli_sum_norm2(ps_handle* h, double* out);
 
 /*
- * pauli_sum_export -- copy up to cap strings to the host, sorted by
- * (x[1], x[0], z[1], z[0]) ascending.  coeffs receives cap*n_lanes values of
- * the handle's dtype (double for PS_F64, float for PS_F32), lane-minor.
- * *n receives the number of strings held; if it exceeds cap nothing is written
- * and PS_ERR_CAPACITY is returned.
+ * pauli_sum_export -- the operator as the list of tuples (I, O_I) of its
+ * strings (Appendix A, the representation each process holds), copied to the
+ * host: up to cap strings, sorted by (x[1], x[0], z[1], z[0]) ascending.
+ * coeffs receives cap*n_lanes values of the handle's dtype (double for
+ * PS_F64, float for PS_F32), lane-minor.  *n receives the number of strings
+ * held; if it exceeds cap nothing is written and PS_ERR_CAPACITY is returned.
+ * pauli_sum_create of the exported tuples (same dtype) restores the same
+ * strings and coefficients (checkpoint and resume).
  */
 int pauli_sum_export(ps_handle* h, ps_pauli* keys, void* coeffs, size_t cap, size_t* n);
 

@@ -177,6 +177,12 @@ struct ps_handle {
     hipEvent_t sort_ev[2] = {nullptr, nullptr};
     int sort_last = 0;
     double radix_sorts = 0;
+    // binary32 general gates: low words of the branch's products, one array
+    // per state buffer (allocated with the auxiliaries once the handle has
+    // run such a gate); lo_live while a general gate's entries carry them
+    bool has_lo = false;
+    bool lo_live = false;
+    float* lo[2] = {nullptr, nullptr};
     // general gates: runs of the last branch (-1: unsorted output, radix
     // sort), the merge-path split buffer and the count of run merges
     int gen_run_bits = -1;
@@ -201,6 +207,7 @@ struct Aux {
     size_t status_words = 0;
     uint64_t max_tiles = 0;
     float* gscore = nullptr;
+    float* lo[2] = {nullptr, nullptr};
 };
 
 bool grab(void** p, size_t bytes) {
@@ -229,7 +236,7 @@ bool alloc_state(ps_handle* h, size_t cap, Buf* b) {
 }
 
 void free_aux(Aux* a) {
-    void* ps[] = {a->rank[0], a->rank[1], a->desc, a->status, a->gscore};
+    void* ps[] = {a->rank[0], a->rank[1], a->desc, a->status, a->gscore, a->lo[0], a->lo[1]};
     for (void* p : ps)
         if (p) (void)hipFree(p);
     *a = Aux{};
@@ -248,6 +255,9 @@ bool alloc_aux(ps_handle* h, size_t cap, bool with_score, Aux* a) {
               grab(reinterpret_cast<void**>(&a->desc), (mt + 2) * sizeof(TileDesc)) &&
               grab(reinterpret_cast<void**>(&a->status), words * sizeof(uint64_t));
     if (ok && with_score) ok = grab(reinterpret_cast<void**>(&a->gscore), cap * sizeof(float));
+    if (ok && h->has_lo)
+        ok = grab(reinterpret_cast<void**>(&a->lo[0]), cap * h->LP * sizeof(float)) &&
+             grab(reinterpret_cast<void**>(&a->lo[1]), cap * h->LP * sizeof(float));
     // status words start from a zero epoch tag the kernels never use (epoch starts at 1)
     if (ok) ok = hipMemsetAsync(a->status, 0, words * sizeof(uint64_t), h->stream) == hipSuccess;
     if (!ok) {
@@ -268,6 +278,9 @@ Aux take_aux(ps_handle* h) {
     a.status_words = h->status_words;
     a.max_tiles = h->max_tiles;
     a.gscore = h->gscore;
+    a.lo[0] = h->lo[0];
+    a.lo[1] = h->lo[1];
+    h->lo[0] = h->lo[1] = nullptr;
     h->rank[0] = h->rank[1] = nullptr;
     h->desc = nullptr;
     h->status = nullptr;
@@ -283,6 +296,8 @@ void put_aux(ps_handle* h, const Aux& a) {
     h->status_words = a.status_words;
     h->max_tiles = a.max_tiles;
     h->gscore = a.gscore;
+    h->lo[0] = a.lo[0];
+    h->lo[1] = a.lo[1];
 }
 
 void free_buffers(ps_handle* h) {
@@ -581,11 +596,35 @@ GenArgs gen_args(ps_handle* h, int in, int out, int mx_in, int mx_out) {
     return a;
 }
 
+// The low-word arrays of binary32 general gates, allocated on first use at
+// the current capacity (later capacities allocate them with the auxiliaries).
+int ensure_lo(ps_handle* h) {
+    if (h->has_lo) return PS_OK;
+    const size_t bytes = h->cap * h->LP * sizeof(float);
+    float* p[2] = {nullptr, nullptr};
+    if (!grab(reinterpret_cast<void**>(&p[0]), bytes) || !grab(reinterpret_cast<void**>(&p[1]), bytes)) {
+        if (p[0]) (void)hipFree(p[0]);
+        return fail(PS_ERR_CAPACITY, "hipMalloc failed for the binary32 low words (%zu strings)", h->cap);
+    }
+    h->lo[0] = p[0];
+    h->lo[1] = p[1];
+    h->has_lo = true;
+    return PS_OK;
+}
+
 // General gate, first half: parents and children of every string, in input
 // order and in the stored x frame; tagged by sorted run when the generator
-// flips few key bits.
+// flips few key bits.  In binary32 every output also carries the low word of
+// its product (lo_live until the equal-key pass has consumed them).
 int enqueue_gen_branch(ps_handle* h, int in, int out, int mx_in, double eps_in, const Stage& st) {
     GenArgs a = gen_args(h, in, out, mx_in, 1 - mx_in);
+    h->lo_live = false;
+    if (h->dtype == PS_F32) {
+        const int rc = ensure_lo(h);
+        if (rc) return rc;
+        a.Lout = h->lo[out];
+        h->lo_live = true;
+    }
     a.eps_in = eps_in;
     a.xrot = h->xrot;
     a.xj0 = st.gen.x[0];
@@ -629,6 +668,8 @@ int enqueue_gen_branch(ps_handle* h, int in, int out, int mx_in, double eps_in, 
 // `out`, with the max of the result in slot mx_out.
 int enqueue_gen_reduce(ps_handle* h, int in, int out, int mx_out) {
     GenArgs a = gen_args(h, in, out, 1 - mx_out, mx_out);
+    a.Lin = h->lo_live ? h->lo[in] : nullptr;
+    h->lo_live = false;
     size_t slot;
     int rc = ev_begin(h, 1, &slot);
     if (rc) return rc;
@@ -767,6 +808,10 @@ int merge_gen_runs(ps_handle* h, int b, int bits, int* result) {
     a.status = h->status;
     a.max_tiles = h->status_words / 256;
     a.dst_buf = 1 - b;
+    if (h->lo_live) {
+        a.Ls = h->lo[b];
+        a.Ld = h->lo[1 - b];
+    }
     size_t slot;
     rc = ev_begin(h, 2, &slot);
     if (rc) return rc;
@@ -801,6 +846,10 @@ int merge_gen_runs(ps_handle* h, int b, int bits, int* result) {
         m.Zd = h->buf[1 - src].Z;
         m.Cd = h->buf[1 - src].C;
         m.split = h->msplit;
+        if (h->lo_live) {
+            m.Ls = h->lo[src];
+            m.Ld = h->lo[1 - src];
+        }
         rc = ev_begin(h, 2, &slot);
         if (rc) return rc;
         HIP_TRY(launch_merge_pairs(m, h->dtype, h->LP, h->stream));
@@ -873,6 +922,10 @@ int sort_by_rank_z(ps_handle* h, int b, int* result, bool full_key = false, bool
         g.Xd = h->buf[1 - b].X;
         g.Zd = h->buf[1 - b].Z;
         g.Cd = h->buf[1 - b].C;
+        if (h->lo_live) {
+            g.Ls = h->lo[b];
+            g.Ld = h->lo[1 - b];
+        }
         size_t slot;
         rc = ev_begin(h, 2, &slot);
         if (rc) return rc;
@@ -959,6 +1012,10 @@ int sort_by_rank_z(ps_handle* h, int b, int* result, bool full_key = false, bool
         a.status = h->status;
         a.max_tiles = h->status_words / 256;
         a.dst_buf = dst;
+        if (h->lo_live) {
+            a.Ls = h->lo[src];
+            a.Ld = h->lo[dst];
+        }
         size_t slot;
         rc = ev_begin(h, 2, &slot);
         if (rc) return rc;
@@ -1243,6 +1300,7 @@ int apply_rotation_layer(ps_handle* h, const ps_pauli* gens, const double* theta
     if (!h) return fail(PS_ERR_INVALID, "handle is NULL");
     if (h->broken) return fail(PS_ERR_DEVICE, "handle is no longer usable after a device failure");
     h->gates_applied = 0;
+    h->lo_live = false;
     if (n_gates == 0) return PS_OK;
     if (!gens || !thetas) return fail(PS_ERR_INVALID, "gens/thetas NULL");
     if (trunc_mode != PS_TRUNC_NONE && trunc_mode != PS_TRUNC_MAGNITUDE && trunc_mode != PS_TRUNC_LEARNED)

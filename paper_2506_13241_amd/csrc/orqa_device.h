@@ -204,52 +204,69 @@ constexpr int kLb2Sleep = 40;
 // the group's inclusive prefix (after it) in gst[group].  A tile sums the
 // tiles of its own group that precede it, then walks back over groups, 64
 // groups (4096 tiles) per round trip: the inclusive prefixes no longer have to
-// creep forward 64 tiles per round trip.  Must be called by all 64 lanes of
-// one wave; returns the exclusive prefix of `tile` (uniform).  Every wait is
-// on tiles or groups that took their indices earlier, and a group's aggregate
-// is formed by its last tile from aggregates that are published without
-// waiting, so every wait ends.
-__device__ __forceinline__ uint64_t lookback_wave2(uint64_t* st, uint64_t* gst, uint32_t tile, uint32_t ep,
-                                                   uint64_t agg, uint32_t* err) {
+// creep forward 64 tiles per round trip.
+//
+// It comes in two halves so that a workgroup can publish a tile's aggregate,
+// do other work, and resolve the tile's prefix later: lb2_publish and
+// lb2_resolve, each called by all 64 lanes of one wave.  Every wait is on
+// tiles or groups that took their indices earlier, and both the aggregates
+// and a group's aggregate (formed by the group's last tile in lb2_publish
+// from its group's aggregates) are published before their tile waits for
+// any prefix, so every wait ends as long as each tile's aggregate is
+// published before its workgroup waits in lb2_resolve for a later tile.
+
+// Publish the aggregate of `tile` (tile 0: its inclusive prefix); the last
+// tile of a group then publishes the group's status.
+__device__ __forceinline__ void lb2_publish(uint64_t* st, uint64_t* gst, uint32_t tile, uint32_t ep, uint64_t agg,
+                                            uint32_t* err) {
     const int lane = lane_id();
-    const uint32_t grp = tile >> 6, first = grp << 6;
-    const bool last_in_group = (tile & 63u) == 63u;
     if (tile == 0) {
         if (lane == 0) st_rel(st, st_pack(ep, 2, agg));
-        return 0;
+        return;
     }
     if (lane == 0) st_rel(st + tile, st_pack(ep, 1, agg));
+    if ((tile & 63u) != 63u) return;
+    // Scanning the group from its end (lane 0 = this tile), the words up to
+    // the first inclusive prefix give the group's inclusive prefix; with
+    // none, all 64 aggregates give the group aggregate.  (A tile's word may
+    // already hold its inclusive prefix instead of its aggregate, so the
+    // scan stops there.)
+    const uint64_t t0 = wall_clock64();
+    uint64_t v;
+    int fi = 64;
+    while (true) {
+        v = ld_acq(st + tile - lane);
+        const uint32_t fl = st_flag(v, ep);
+        const uint64_t incl = __ballot(fl == 2u);
+        const uint64_t pend = __ballot(fl == 0u);
+        fi = incl ? (__ffsll(static_cast<unsigned long long>(incl)) - 1) : 64;
+        const int fr = pend ? (__ffsll(static_cast<unsigned long long>(pend)) - 1) : 64;
+        if (fr > fi || fr == 64) break;
+        if (__any(wall_clock64() - t0 > kLookbackTicks)) {
+            if (lane == 0) atomicOr(err, kErrLookback);
+            return;
+        }
+        __builtin_amdgcn_s_sleep(kLb2Sleep);
+    }
+    const uint64_t gsum = wave_sum_u64(lane <= fi ? (v & kValMask) : 0ull);
+    if (lane == 0) st_rel(gst + (tile >> 6), st_pack(ep, fi < 64 ? 2u : 1u, gsum));
+}
+
+// Exclusive prefix of `tile` (uniform), whose aggregate `agg` lb2_publish has
+// published; publishes the tile's (and, for the last tile of a group, the
+// group's) inclusive prefix.
+__device__ __forceinline__ uint64_t lb2_resolve(uint64_t* st, uint64_t* gst, uint32_t tile, uint32_t ep,
+                                                uint64_t agg, uint32_t* err) {
+    const int lane = lane_id();
+    if (tile == 0) return 0;
+    const uint32_t grp = tile >> 6, first = grp << 6;
+    const bool last_in_group = (tile & 63u) == 63u;
     const uint64_t t0 = wall_clock64();
     bool timed_out = false;
-    // The last tile of a group publishes the group's status first: scanning
-    // the group from its end (lane 0 = this tile), the words up to the first
-    // inclusive prefix give the group's inclusive prefix; with none, all 64
-    // aggregates give the group aggregate.  (A tile's word may already hold
-    // its inclusive prefix instead of its aggregate, so the scan stops there.)
-    if (last_in_group) {
-        uint64_t v;
-        int fi = 64;
-        while (true) {
-            v = ld_acq(st + tile - lane);
-            const uint32_t fl = st_flag(v, ep);
-            const uint64_t incl = __ballot(fl == 2u);
-            const uint64_t pend = __ballot(fl == 0u);
-            fi = incl ? (__ffsll(static_cast<unsigned long long>(incl)) - 1) : 64;
-            const int fr = pend ? (__ffsll(static_cast<unsigned long long>(pend)) - 1) : 64;
-            if (fr > fi || fr == 64) break;
-            if (__any(wall_clock64() - t0 > kLookbackTicks)) {
-                timed_out = true;
-                break;
-            }
-            __builtin_amdgcn_s_sleep(kLb2Sleep);
-        }
-        const uint64_t gsum = wave_sum_u64((!timed_out && lane <= fi) ? (v & kValMask) : 0ull);
-        if (lane == 0 && !timed_out) st_rel(gst + grp, st_pack(ep, fi < 64 ? 2u : 1u, gsum));
-    }
     uint64_t excl = 0;
     bool done = false;
     // ---- within the group: tiles first .. tile-1, nearest first
-    if (!timed_out && tile > first) {
+    if (tile > first) {
         const int64_t j = int64_t(tile) - 1 - lane;
         const bool in = j >= int64_t(first);
         uint64_t v = 0;
@@ -319,6 +336,13 @@ __device__ __forceinline__ uint64_t lookback_wave2(uint64_t* st, uint64_t* gst, 
         if (last_in_group) st_rel(gst + grp, st_pack(ep, 2, excl + agg));
     }
     return excl;
+}
+
+// Both halves back to back: the exclusive prefix of `tile` (uniform).
+__device__ __forceinline__ uint64_t lookback_wave2(uint64_t* st, uint64_t* gst, uint32_t tile, uint32_t ep,
+                                                   uint64_t agg, uint32_t* err) {
+    lb2_publish(st, gst, tile, ep, agg, err);
+    return lb2_resolve(st, gst, tile, ep, agg, err);
 }
 
 // Single-thread look-back (one channel per thread, used by the radix sort with

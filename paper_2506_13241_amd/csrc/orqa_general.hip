@@ -147,6 +147,10 @@ __global__ __launch_bounds__(kThreads) void k_gen_branch(GenArgs A, GateTrig g) 
                     A.Zout[o] = zs[k];
 #pragma unroll
                     for (int a = 0; a < LP; ++a) Cout[o * LP + a] = ce[a];
+                    if (A.Lout) {
+#pragma unroll
+                        for (int a = 0; a < LP; ++a) A.Lout[o * LP + a] = 0.0f;
+                    }
                     if (A.Tout) A.Tout[o] = 0u;
                 }
                 ++o;
@@ -156,8 +160,20 @@ __global__ __launch_bounds__(kThreads) void k_gen_branch(GenArgs A, GateTrig g) 
                 if (o < A.cap) {
                     A.Xout[o] = xw;
                     A.Zout[o] = zs[k];
+                    if constexpr (sizeof(CT) == 4) {
+                        if (A.Lout) {
 #pragma unroll
-                    for (int a = 0; a < LP; ++a) Cout[o * LP + a] = Arith<CT>::scale_c(g, a, ce[a]);
+                            for (int a = 0; a < LP; ++a) {
+                                const F32x2 p = mul_split(ce[a], g.cs_hi[a], g.cs_lo[a]);
+                                Cout[o * LP + a] = p.hi;
+                                A.Lout[o * LP + a] = p.lo;
+                            }
+                        }
+                    }
+                    if (sizeof(CT) != 4 || !A.Lout) {
+#pragma unroll
+                        for (int a = 0; a < LP; ++a) Cout[o * LP + a] = Arith<CT>::scale_c(g, a, ce[a]);
+                    }
                     if (A.Tout) A.Tout[o] = 0u;
                 }
                 ++o;
@@ -169,8 +185,22 @@ __global__ __launch_bounds__(kThreads) void k_gen_branch(GenArgs A, GateTrig g) 
                 if (o < A.cap) {
                     A.Xout[o] = make_ulonglong2(xw.x ^ xjs.x, xw.y ^ xjs.y);
                     A.Zout[o] = zc;
+                    if constexpr (sizeof(CT) == 4) {
+                        if (A.Lout) {
 #pragma unroll
-                    for (int a = 0; a < LP; ++a) Cout[o * LP + a] = Arith<CT>::scale_s(g, a, ce[a], neg);
+                            for (int a = 0; a < LP; ++a) {
+                                const float h = neg ? -g.sn_hi[a] : g.sn_hi[a];
+                                const float l = neg ? -g.sn_lo[a] : g.sn_lo[a];
+                                const F32x2 p = mul_split(ce[a], h, l);
+                                Cout[o * LP + a] = p.hi;
+                                A.Lout[o * LP + a] = p.lo;
+                            }
+                        }
+                    }
+                    if (sizeof(CT) != 4 || !A.Lout) {
+#pragma unroll
+                        for (int a = 0; a < LP; ++a) Cout[o * LP + a] = Arith<CT>::scale_s(g, a, ce[a], neg);
+                    }
                     if (A.Tout) A.Tout[o] = 1u + run_class(A, xw, zs[k]);
                 }
                 ++o;
@@ -251,7 +281,20 @@ __global__ __launch_bounds__(kThreads) void k_gen_reduce(GenArgs A) {
 #pragma unroll
             for (int a = 0; a < LP; ++a) {
                 CT v = Cin[i * LP + a];
-                if (two) v = v + Cin[(i + 1) * LP + a];
+                bool done = false;
+                if constexpr (sizeof(CT) == 4) {
+                    if (A.Lin) {  // unevaluated pairs: two-sum of the heads, one rounding
+                        const float l1 = A.Lin[i * LP + a];
+                        if (two) {
+                            const F32x2 s = two_sum(v, Cin[(i + 1) * LP + a]);
+                            v = s.hi + (s.lo + (l1 + A.Lin[(i + 1) * LP + a]));
+                        } else {
+                            v = v + l1;
+                        }
+                        done = true;
+                    }
+                }
+                if (!done && two) v = v + Cin[(i + 1) * LP + a];
                 Cout[o * LP + a] = v;
                 vmax[a] = fmax(vmax[a], absd(v));
             }
@@ -363,6 +406,10 @@ __global__ __launch_bounds__(kThreads) void k_merge_pairs(MergeArgs A) {
         A.Zd[out] = sZ[l];
 #pragma unroll
         for (int a = 0; a < LP; ++a) Cd[out * LP + a] = Cs[src * LP + a];
+        if (A.Ls) {
+#pragma unroll
+            for (int a = 0; a < LP; ++a) A.Ld[out * LP + a] = A.Ls[src * LP + a];
+        }
     }
 }
 

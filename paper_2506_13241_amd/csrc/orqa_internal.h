@@ -22,6 +22,7 @@ constexpr int kThreads = 256;
 constexpr int kRxIPT = 3;
 constexpr int kRxTileMax = kThreads * kRxIPT;  // 768
 constexpr int kRxTile = kRxTileMax - 2;        // 766
+constexpr int kRxHold = 4;  // output entries per thread an RX workgroup holds in registers across tiles
 constexpr int kCompactIPT = 4;
 constexpr int kCompactTile = kThreads * kCompactIPT;  // 1024
 constexpr int kSortIPT = 8;                     // smallest items per thread of a sort pass
@@ -95,8 +96,8 @@ struct RxArgs {
     ulonglong2* Zout;
     void* Cout;
     uint64_t cap;
-    TileDesc* desc;
-    uint64_t* status;  // 2 x max_tiles
+    TileDesc* desc;    // tile boundaries (k_rx_partition), ntiles + 1
+    uint64_t* status;  // 2 x (max_tiles + max_tiles / 64 + 2): tile words, then group words, per channel
     uint64_t max_tiles;
     double eps_in;     // pending truncation of the input (<= 0: none)
     int nq;
@@ -155,6 +156,10 @@ struct SortPassArgs {
     uint64_t* status;        // max_tiles x 256
     uint64_t max_tiles;
     int dst_buf;
+    // binary32 general gates: the low words of the branch's products (n x
+    // lanes), moved with the strings; NULL otherwise
+    const float* Ls;
+    float* Ld;
 };
 
 // Host-side launchers (orqa_kernels.hip), dispatching on dtype and padded lanes.
@@ -181,6 +186,8 @@ struct GroupSortArgs {
     ulonglong2* Xd;
     ulonglong2* Zd;
     void* Cd;
+    const float* Ls;  // low words moved with the strings (binary32 general gates), or NULL
+    float* Ld;
 };
 hipError_t launch_group_sort(const GroupSortArgs& a, int dtype, int lp, hipStream_t s, int grid);
 
@@ -211,6 +218,12 @@ struct GenArgs {
     int run_bits;
     uint8_t run_pos[6];
     uint8_t run_isz[6];
+    // binary32: the branch writes each output as an unevaluated pair, the
+    // rounded product in Cout and its low word in Lout (the exact product of
+    // the split cos / sin, Arith<float>); the equal-key pass sums the pairs of
+    // a key with two-sum and rounds once (Lin).  NULL for binary64.
+    float* Lout;
+    const float* Lin;
 };
 constexpr int kRunMaxBits = 6;  // at most 1 + 2^6 sorted runs per general gate
 
@@ -235,6 +248,8 @@ struct MergeArgs {
     ulonglong2* Zd;
     void* Cd;
     uint64_t* split;  // per tile: A elements before its first output (within its pair)
+    const float* Ls;  // low words moved with the strings (binary32 general gates), or NULL
+    float* Ld;
 };
 hipError_t launch_merge_pairs(const MergeArgs& a, int dtype, int lp, hipStream_t s);
 hipError_t launch_gen_branch(const GenArgs& a, const GateTrig& g, int dtype, int lp, hipStream_t s, int grid);

@@ -18,8 +18,10 @@ namespace orqa {
 // ================================================================ RX: tile split
 // Sorted order of the input: (X, z).  A pairing block = equal X with bit 0
 // cleared.  Merged order inside a block: by z, A before B on ties, so a
-// string and its partner are adjacent.  split(b) returns the input positions
-// where merged position b falls, moved by one when b would separate a pair.
+// string and its partner are adjacent.  Merging permutes strings only inside
+// their block, so merged position b and input position b lie in the same
+// block; tile t covers merged positions [t kRxTile, (t+1) kRxTile), its
+// boundaries moved by one where they would separate a pair.
 
 struct VIn {
     const ulonglong2* X;
@@ -29,82 +31,73 @@ struct VIn {
     __device__ __forceinline__ ulonglong2 z(uint64_t i) const { return Z[vphys(i, nf, cap)]; }
 };
 
-// first i in [lo, hi) with h(X[i]) >= key (hi if none)
-__device__ uint64_t first_h_geq(const VIn& v, ulonglong2 key, uint64_t lo, uint64_t hi) {
+// First index in [lo, hi) where pred holds, hi if none; pred must be
+// monotone in the index (false ... false true ... true).  Called by all 64
+// lanes of a wave with uniform bounds: each round probes 64 evenly spaced
+// indices and shrinks the range 64-fold, so a range of up to 64 takes one
+// round trip to memory.
+template <class Pred>
+__device__ __forceinline__ uint64_t wave_lower_bound(uint64_t lo, uint64_t hi, Pred pred) {
+    const uint64_t lane = uint64_t(lane_id());
     while (lo < hi) {
-        const uint64_t mid = lo + (hi - lo) / 2;
-        if (k_lt(k_h(v.x(mid)), key)) lo = mid + 1;
-        else hi = mid;
-    }
-    return lo;
-}
-// first i in [lo, hi) with h(X[i]) > key
-__device__ uint64_t first_h_gt(const VIn& v, ulonglong2 key, uint64_t lo, uint64_t hi) {
-    while (lo < hi) {
-        const uint64_t mid = lo + (hi - lo) / 2;
-        if (k_le(k_h(v.x(mid)), key)) lo = mid + 1;
-        else hi = mid;
-    }
-    return lo;
-}
-// first i in [lo, hi) with X[i] >= key
-__device__ uint64_t first_x_geq(const VIn& v, ulonglong2 key, uint64_t lo, uint64_t hi) {
-    while (lo < hi) {
-        const uint64_t mid = lo + (hi - lo) / 2;
-        if (k_lt(v.x(mid), key)) lo = mid + 1;
-        else hi = mid;
+        const uint64_t step = (hi - lo + 63) >> 6;
+        const uint64_t q = lo + (lane + 1) * step - 1;
+        const uint64_t bal = __ballot(q >= hi || pred(q));
+        if (bal == 0) return hi;  // then lane 63 probed hi - 1
+        const uint64_t L = uint64_t(__ffsll(static_cast<unsigned long long>(bal)) - 1);
+        const uint64_t qL = lo + (L + 1) * step - 1;
+        lo += L * step;
+        if (qL < hi) hi = qL;
     }
     return lo;
 }
 
-__device__ TileDesc rx_split(const VIn& v, uint64_t n, uint64_t b) {
+// Split of merged position b (all 64 lanes, uniform result): the input
+// positions where it falls in the A and B groups of its pairing block, the
+// block's first B position and its end.  One window of 128 keys around b
+// usually settles the block; wider blocks take 64-ary searches.
+__device__ TileDesc wave_split(const VIn& v, uint64_t n, uint64_t b) {
     if (b >= n) return {n, n, n, n};
+    const int lane = lane_id();
     const ulonglong2 H = k_h(v.x(b));
-    // block start: gallop backwards
-    uint64_t r = b, lo;
-    for (uint64_t step = 1;; step <<= 1) {
-        if (r < step) {
-            lo = 0;
-            break;
-        }
-        const uint64_t c = r - step;
-        if (k_lt(k_h(v.x(c)), H)) {
-            lo = c + 1;
-            break;
-        }
-        r = c;
+    const ulonglong2 H1 = make_ulonglong2(H.x | 1ull, H.y);
+    // lane l reads positions b - 64 + l and b + l
+    const int64_t pb = int64_t(b) - 64 + lane;
+    const uint64_t pf = b + uint64_t(lane);
+    const ulonglong2 xb = pb >= 0 ? v.x(uint64_t(pb)) : make_ulonglong2(0, 0);
+    const ulonglong2 xf = pf < n ? v.x(pf) : make_ulonglong2(0, 0);
+    // block start: h is non-decreasing, so the lanes before the block form a prefix
+    const uint64_t before = __ballot(pb < 0 || k_lt(k_h(xb), H));
+    const uint64_t hs = before != 0
+                            ? uint64_t(int64_t(b) - 64 + __popcll(before))
+                            : wave_lower_bound(0, b - 64, [&](uint64_t i) { return !k_lt(k_h(v.x(i)), H); });
+    // block end (lane 0 reads b itself, which is inside)
+    const uint64_t after = __ballot(pf >= n || k_lt(H, k_h(xf)));
+    const uint64_t he = after != 0
+                            ? b + uint64_t(__ffsll(static_cast<unsigned long long>(after)) - 1)
+                            : wave_lower_bound(b + 64, n, [&](uint64_t i) { return k_lt(H, k_h(v.x(i))); });
+    // first B string of the block
+    uint64_t hm;
+    if (before != 0 && after != 0) {
+        const uint64_t mb = __ballot(pb >= int64_t(hs) && !k_lt(xb, H1));
+        const uint64_t mf = __ballot(pf < he && !k_lt(xf, H1));
+        hm = mb ? uint64_t(int64_t(b) - 64 + (__ffsll(static_cast<unsigned long long>(mb)) - 1))
+                : (mf ? b + uint64_t(__ffsll(static_cast<unsigned long long>(mf)) - 1) : he);
+    } else {
+        hm = wave_lower_bound(hs, he, [&](uint64_t i) { return !k_lt(v.x(i), H1); });
     }
-    const uint64_t hs = first_h_geq(v, H, lo, r);
-    // block end: gallop forwards
-    uint64_t l = b, hi;
-    for (uint64_t step = 1;; step <<= 1) {
-        const uint64_t c = l + step;
-        if (c >= n) {
-            hi = n;
-            break;
-        }
-        if (k_lt(H, k_h(v.x(c)))) {
-            hi = c;
-            break;
-        }
-        l = c;
-    }
-    const uint64_t he = first_h_gt(v, H, l + 1, hi);
-    const uint64_t hm = first_x_geq(v, make_ulonglong2(H.x | 1ull, H.y), hs, he);
     const uint64_t na = hm - hs, nbb = he - hm, d = b - hs;
     // merge path: i = number of A strings among the first d merged
-    uint64_t ilo = d > nbb ? d - nbb : 0, ihi = d < na ? d : na;
-    while (ilo < ihi) {
-        const uint64_t mid = ilo + (ihi - ilo) / 2;
-        if (k_le(v.z(hs + mid), v.z(hm + d - 1 - mid))) ilo = mid + 1;
-        else ihi = mid;
-    }
-    const uint64_t i = ilo;
+    const uint64_t ilo = d > nbb ? d - nbb : 0, ihi = d < na ? d : na;
+    const uint64_t i = wave_lower_bound(
+        ilo, ihi, [&](uint64_t mid) { return !k_le(v.z(hs + mid), v.z(hm + d - 1 - mid)); });
     uint64_t k = d - i;
     if (i > 0 && k < nbb && k_eq(v.z(hs + i - 1), v.z(hm + k))) k += 1;  // keep the pair together
     return {hs + i, hm + k, hm, he};
 }
 
+// One wave per tile boundary: desc[t] = split of merged position t kRxTile for
+// t = 0 .. ntiles (the last one at n).
 __global__ __launch_bounds__(kThreads) void k_rx_partition(const Ctrl* __restrict__ ctrl, int in_buf,
                                                            const ulonglong2* __restrict__ X,
                                                            const ulonglong2* __restrict__ Z, uint64_t cap,
@@ -113,10 +106,11 @@ __global__ __launch_bounds__(kThreads) void k_rx_partition(const Ctrl* __restric
     const uint64_t nf = ctrl->nf[in_buf], n = nf + ctrl->nb[in_buf];
     const uint64_t ntiles = (n + kRxTile - 1) / kRxTile;
     const VIn v{X, Z, nf, cap};
-    for (uint64_t t = blockIdx.x * uint64_t(blockDim.x) + threadIdx.x; t <= ntiles;
-         t += uint64_t(gridDim.x) * blockDim.x) {
+    const uint64_t waves = uint64_t(gridDim.x) * (kThreads / 64);
+    for (uint64_t t = blockIdx.x * uint64_t(kThreads / 64) + (threadIdx.x >> 6); t <= ntiles; t += waves) {
         const uint64_t b = t * kRxTile;
-        desc[t] = rx_split(v, n, b < n ? b : n);
+        const TileDesc d = wave_split(v, n, b < n ? b : n);
+        if (lane_id() == 0) desc[t] = d;
     }
 }
 
@@ -129,7 +123,6 @@ __device__ __forceinline__ bool keep_row(const CT* c, const double* thr) {
     return keep;
 }
 
-
 // Input ranges of one RX tile (uniform across the workgroup).
 struct RxTile {
     uint64_t r1s, r2s, r3s;
@@ -137,8 +130,17 @@ struct RxTile {
     bool sane;
 };
 
-__device__ __forceinline__ RxTile rx_tile(const TileDesc* desc, uint32_t tile, uint64_t n) {
-    const TileDesc d0 = desc[tile], d1 = desc[tile + 1];
+__device__ __forceinline__ uint64_t uni64(uint64_t v) {
+    const uint32_t lo = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(v));
+    const uint32_t hi = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(v >> 32));
+    return (static_cast<uint64_t>(hi) << 32) | lo;
+}
+
+// Tile ranges from the descriptors of its two boundaries (uniform values,
+// kept in scalar registers).
+__device__ __forceinline__ RxTile rx_tile(const TileDesc& e0, const TileDesc& e1, uint64_t n) {
+    const TileDesc d0{uni64(e0.posA), uni64(e0.posB), uni64(e0.hm), uni64(e0.he)};
+    const TileDesc d1{uni64(e1.posA), uni64(e1.posB), uni64(e1.hm), uni64(e1.he)};
     const bool same = (d0.hm == d1.hm) && (d0.he == d1.he);
     const uint64_t r1s = d0.posA, r1e = same ? d1.posA : d0.hm;
     const uint64_t r2s = d0.posB, r2e = same ? d1.posB : d1.posA;
@@ -171,8 +173,29 @@ __device__ __forceinline__ uint32_t out_entry(uint32_t e, uint32_t e2, uint32_t 
 }
 
 template <typename CT, int LP>
-__global__ __launch_bounds__(kThreads) void k_rx_merge(RxArgs A, GateTrig g) {
-    constexpr bool kStageC = LP * sizeof(CT) <= 8;  // coefficients staged in LDS
+__device__ __forceinline__ CT rx_value(const GateTrig& g, int a, uint32_t kind, bool neg, CT ce, CT ce2) {
+    if (kind == 0) return ce;
+    if (kind == 1) return Arith<CT>::scale_c(g, a, ce);
+    if (kind == 2) return Arith<CT>::scale_s(g, a, ce, neg);
+    return Arith<CT>::pair(g, a, ce, ce2, neg);
+}
+
+constexpr uint32_t kNoTile = 0xFFFFFFFFu;
+
+// One RX gate, software-pipelined over the tiles a workgroup takes: a tile is
+// loaded and planned (x-groups, merged order, emission plan, output counts),
+// its output counts published, and its outputs gathered into registers; they
+// are written one iteration later, once the look-back has resolved the
+// tile's output offsets, so the wait for those offsets overlaps the loading
+// and planning of the next tile.  The split descriptors of the next tile are
+// found by two waves during the same wait.  A tile with more outputs than
+// the registers hold (KR per thread) is resolved and written at once; with
+// KR = 0 (rows of several coefficients, which do not fit in registers) every
+// tile is.
+template <typename CT, int LP, int KR>
+__device__ __forceinline__ void rx_merge_body(const RxArgs& A, const GateTrig& g) {
+    constexpr bool kStageC = LP * sizeof(CT) <= 8;  // coefficients staged in LDS (and held in registers)
+    constexpr int KH = KR > 0 ? KR : 1;             // size of the hold arrays
     __shared__ ulonglong2 sX[kRxTileMax];
     __shared__ ulonglong2 sZ[kRxTileMax];
     __shared__ CT sC[kStageC ? kRxTileMax * LP : 1];
@@ -200,245 +223,346 @@ __global__ __launch_bounds__(kThreads) void k_rx_merge(RxArgs A, GateTrig g) {
     double vmax[LP];
 #pragma unroll
     for (int a = 0; a < LP; ++a) vmax[a] = 0.0;
-    __syncthreads();
     const int zw = g.zword;
     const uint64_t zmask = 1ull << g.zbit;
     const uint64_t cap = A.cap;
+    // look-back channels: wave 0 the front run, wave 1 the back run
+    const uint64_t gmax = A.max_tiles / 64 + 2;
+    uint64_t* const st = A.status + (wave & 1) * A.max_tiles;
+    uint64_t* const gst = A.status + 2 * A.max_tiles + (wave & 1) * gmax;
 
+    // the held tile: planned, counts published, outputs in registers
+    uint32_t h_tile = kNoTile, h_totA = 0, h_totB = 0;
+    uint64_t hxl[KH], hxh[KH], hzl[KH], hzh[KH];  // (scalar words: kept in registers)
+    CT hc[KH][kStageC ? LP : 1];
+    uint64_t hp1[kStageC ? 1 : KH], hp2[kStageC ? 1 : KH];
+    uint32_t hk[kStageC ? 1 : KH];
+
+    // Each iteration takes a tile (while there are tiles: a tile is taken
+    // only when the workgroup is about to load it, so that no tile waits
+    // unpublished behind another tile's look-back), writes the tile held from
+    // the iteration before, and holds the new one.
+    uint32_t tile = acquire_tile(ctrl, &sTile);
     for (;;) {
-        const uint32_t tile = acquire_tile(ctrl, &sTile);
-        if (tile >= ntiles) break;
-        const RxTile T = rx_tile(A.desc, tile, n);
-        if (!T.sane && tid == 0) atomicOr(&ctrl->err, kErrInternal);
-        const uint32_t m = T.m;
+        const bool have = tile < ntiles;
+        if (!have && h_tile == kNoTile) break;
+        RxTile T{};
+        uint32_t totA = 0, totB = 0;
+        if (have) {
+            T = rx_tile(A.desc[tile], A.desc[tile + 1], n);
+            if (!T.sane && tid == 0) atomicOr(&ctrl->err, kErrInternal);
+            const uint32_t m = T.m;
 
-        // ---- keys (and coefficients) of the tile into LDS.  Every slot loads
-        // (slots past the tile end re-read string 0 of the tile), so the values
-        // stay in registers and all loads are in flight together.
-        if (m > 0) {
-            uint64_t rxl[kRxIPT], rxh[kRxIPT], rzl[kRxIPT], rzh[kRxIPT];
-            CT rc[kRxIPT][kStageC ? LP : 1];
+            // ---- keys (and coefficients) of the tile into LDS.  Every slot loads
+            // (slots past the tile end re-read string 0 of the tile), so the values
+            // stay in registers and all loads are in flight together.
+            if (m > 0) {
+                uint64_t rxl[kRxIPT], rxh[kRxIPT], rzl[kRxIPT], rzh[kRxIPT];
+                CT rc[kRxIPT][kStageC ? LP : 1];
 #pragma unroll
-            for (int k = 0; k < kRxIPT; ++k) {
-                const uint32_t e = k * kThreads + tid;
-                const uint64_t p = rx_phys(T, e < m ? e : 0u, nf, cap);
-                const ulonglong2 x = A.Xin[p], z = A.Zin[p];
-                rxl[k] = x.x;
-                rxh[k] = x.y;
-                rzl[k] = z.x;
-                rzh[k] = z.y;
-                if constexpr (kStageC) {
-#pragma unroll
-                    for (int a = 0; a < LP; ++a) rc[k][a] = Cin[p * LP + a];
-                }
-            }
-#pragma unroll
-            for (int k = 0; k < kRxIPT; ++k) {
-                const uint32_t e = k * kThreads + tid;
-                if (e < m) {
-                    sX[e] = make_ulonglong2(rxl[k], rxh[k]);
-                    sZ[e] = make_ulonglong2(rzl[k], rzh[k]);
+                for (int k = 0; k < kRxIPT; ++k) {
+                    const uint32_t e = k * kThreads + tid;
+                    const uint64_t p = rx_phys(T, e < m ? e : 0u, nf, cap);
+                    const ulonglong2 x = A.Xin[p], z = A.Zin[p];
+                    rxl[k] = x.x;
+                    rxh[k] = x.y;
+                    rzl[k] = z.x;
+                    rzh[k] = z.y;
                     if constexpr (kStageC) {
-                        bool keep = !filt;
 #pragma unroll
-                        for (int a = 0; a < LP; ++a) {
-                            sC[e * LP + a] = rc[k][a];
-                            keep |= absd(rc[k][a]) > sThr[a];
+                        for (int a = 0; a < LP; ++a) rc[k][a] = Cin[p * LP + a];
+                    }
+                }
+#pragma unroll
+                for (int k = 0; k < kRxIPT; ++k) {
+                    const uint32_t e = k * kThreads + tid;
+                    if (e < m) {
+                        sX[e] = make_ulonglong2(rxl[k], rxh[k]);
+                        sZ[e] = make_ulonglong2(rzl[k], rzh[k]);
+                        if constexpr (kStageC) {
+                            bool keep = !filt;
+#pragma unroll
+                            for (int a = 0; a < LP; ++a) {
+                                sC[e * LP + a] = rc[k][a];
+                                keep |= absd(rc[k][a]) > sThr[a];
+                            }
+                            sAlive[e] = uint8_t(keep);
+                        } else {
+                            sAlive[e] =
+                                filt ? uint8_t(keep_row<CT, LP>(Cin + rx_phys(T, e, nf, cap) * LP, sThr)) : uint8_t(1);
                         }
-                        sAlive[e] = uint8_t(keep);
-                    } else {
-                        sAlive[e] =
-                            filt ? uint8_t(keep_row<CT, LP>(Cin + rx_phys(T, e, nf, cap) * LP, sThr)) : uint8_t(1);
                     }
                 }
             }
-        }
-        __syncthreads();
+            __syncthreads();
 
-        // ---- x-groups ("parts"): ids and starts (blocked: thread owns e0..e0+IPT-1)
-        const uint32_t e0 = tid * kRxIPT;
-        uint32_t flags = 0, cnt = 0;
-#pragma unroll
-        for (int k = 0; k < kRxIPT; ++k) {
-            const uint32_t e = e0 + k;
-            const bool f = e < m && (e == 0 || !k_eq(sX[e], sX[e - 1]));
-            flags |= uint32_t(f) << k;
-            cnt += f;
-        }
-        uint32_t npart;
-        uint32_t pid = block_excl_scan(cnt, sWave, npart);
-        const uint32_t pid0 = pid;
-#pragma unroll
-        for (int k = 0; k < kRxIPT; ++k) {
-            if ((flags >> k) & 1u) sStart[pid++] = uint16_t(e0 + k);
-        }
-        if (tid == 0) {
-            sStart[npart] = uint16_t(m);
-            sStart[npart + 1] = uint16_t(m);
-        }
-        __syncthreads();
-
-        // ---- merged position of every string (merge by z of the two x-groups of a block)
-        {
-            uint32_t p = pid0;
+            // ---- x-groups ("parts"): ids and starts (blocked: thread owns e0..e0+IPT-1)
+            const uint32_t e0 = tid * kRxIPT;
+            uint32_t flags = 0, cnt = 0;
 #pragma unroll
             for (int k = 0; k < kRxIPT; ++k) {
                 const uint32_t e = e0 + k;
-                if (e >= m) continue;
-                if ((flags >> k) & 1u) ++p;
-                const uint32_t mypart = p - 1;
-                const ulonglong2 xe = sX[e], ze = sZ[e];
-                uint32_t os = 0, oe = 0, mpos;
-                if ((xe.x & 1ull) == 0) {
-                    if (mypart + 1 < npart) {
-                        const uint32_t s = sStart[mypart + 1];
-                        if (sX[s].x == (xe.x | 1ull) && sX[s].y == xe.y) {
-                            os = s;
-                            oe = sStart[mypart + 2];
-                        }
-                    }
-                    uint32_t lo = os, hi = oe;  // partner-group strings with z < ze
-                    while (lo < hi) {
-                        const uint32_t mid = (lo + hi) >> 1;
-                        if (k_lt(sZ[mid], ze)) lo = mid + 1;
-                        else hi = mid;
-                    }
-                    mpos = e + (lo - os);
-                } else {
-                    const uint32_t ps = sStart[mypart];
-                    if (mypart >= 1) {
-                        const uint32_t s = sStart[mypart - 1];
-                        if (sX[s].x == (xe.x & ~1ull) && sX[s].y == xe.y) {
-                            os = s;
-                            oe = ps;
-                        }
-                    }
-                    uint32_t lo = os, hi = oe;  // partner-group strings with z <= ze
-                    while (lo < hi) {
-                        const uint32_t mid = (lo + hi) >> 1;
-                        if (k_le(sZ[mid], ze)) lo = mid + 1;
-                        else hi = mid;
-                    }
-                    mpos = e - (oe - os) + (lo - os);
-                }
-                if (mpos < m) sMidx[mpos] = uint16_t(e);
-                else atomicOr(&ctrl->err, kErrInternal);
+                const bool f = e < m && (e == 0 || !k_eq(sX[e], sX[e - 1]));
+                flags |= uint32_t(f) << k;
+                cnt += f;
             }
-        }
-        __syncthreads();
-
-        // ---- emission plan in merged order
-        uint32_t entA[kRxIPT], entB[kRxIPT];
-        uint32_t cntA = 0, cntB = 0;
-#pragma unroll
-        for (int k = 0; k < kRxIPT; ++k) {
-            entA[k] = entB[k] = 0xFFFFFFFFu;
-            const uint32_t q = e0 + k;
-            if (q >= m) continue;
-            const uint32_t e = sMidx[q];
-            if (!sAlive[e]) continue;
-            const ulonglong2 xe = sX[e], ze = sZ[e];
-            const bool isB = xe.x & 1ull;
-            const bool ac = ((zw == 0 ? ze.x : ze.y) & zmask) != 0ull;
-            if (!isB) {
-                uint32_t e2 = 0xFFFFu;
-                if (q + 1 < m) {
-                    const uint32_t c = sMidx[q + 1];
-                    if (sX[c].x == (xe.x | 1ull) && sX[c].y == xe.y && k_eq(sZ[c], ze) && sAlive[c]) e2 = c;
-                }
-                if (e2 != 0xFFFFu) {
-                    entA[k] = out_entry(e, e2, ac ? 3u : 0u);
-                    entB[k] = out_entry(e2, e, ac ? 3u : 0u);
-                } else if (ac) {
-                    if (g.any_c) entA[k] = out_entry(e, 0, 1u);
-                    if (g.any_s) entB[k] = out_entry(e, 0, 2u);
-                } else {
-                    entA[k] = out_entry(e, 0, 0u);
-                }
-            } else {
-                bool paired = false;
-                if (q > 0) {
-                    const uint32_t c = sMidx[q - 1];
-                    paired = sX[c].x == (xe.x & ~1ull) && sX[c].y == xe.y && k_eq(sZ[c], ze) && sAlive[c];
-                }
-                if (paired) {
-                    // emitted by the A string of the pair
-                } else if (ac) {
-                    if (g.any_s) entA[k] = out_entry(e, 0, 2u);
-                    if (g.any_c) entB[k] = out_entry(e, 0, 1u);
-                } else {
-                    entB[k] = out_entry(e, 0, 0u);
-                }
-            }
-            cntA += entA[k] != 0xFFFFFFFFu;
-            cntB += entB[k] != 0xFFFFFFFFu;
-        }
-        uint32_t totPacked;
-        const uint32_t offPacked = block_excl_scan(cntA | (cntB << 16), sWave, totPacked);
-        const uint32_t totA = totPacked & 0xFFFFu, totB = totPacked >> 16;
-        {
-            uint32_t oa = offPacked & 0xFFFFu, ob = offPacked >> 16;
+            uint32_t npart;
+            uint32_t pid = block_excl_scan(cnt, sWave, npart);
+            const uint32_t pid0 = pid;
 #pragma unroll
             for (int k = 0; k < kRxIPT; ++k) {
-                if (entA[k] != 0xFFFFFFFFu) sOut[0][oa++] = entA[k];
-                if (entB[k] != 0xFFFFFFFFu) sOut[1][ob++] = entB[k];
+                if ((flags >> k) & 1u) sStart[pid++] = uint16_t(e0 + k);
             }
+            if (tid == 0) {
+                sStart[npart] = uint16_t(m);
+                sStart[npart + 1] = uint16_t(m);
+            }
+            __syncthreads();
+
+            // ---- merged position of every string (merge by z of the two x-groups of a block)
+            {
+                uint32_t p = pid0;
+#pragma unroll
+                for (int k = 0; k < kRxIPT; ++k) {
+                    const uint32_t e = e0 + k;
+                    if (e >= m) continue;
+                    if ((flags >> k) & 1u) ++p;
+                    const uint32_t mypart = p - 1;
+                    const ulonglong2 xe = sX[e], ze = sZ[e];
+                    uint32_t os = 0, oe = 0, mpos;
+                    if ((xe.x & 1ull) == 0) {
+                        if (mypart + 1 < npart) {
+                            const uint32_t s = sStart[mypart + 1];
+                            if (sX[s].x == (xe.x | 1ull) && sX[s].y == xe.y) {
+                                os = s;
+                                oe = sStart[mypart + 2];
+                            }
+                        }
+                        uint32_t lo = os, hi = oe;  // partner-group strings with z < ze
+                        while (lo < hi) {
+                            const uint32_t mid = (lo + hi) >> 1;
+                            if (k_lt(sZ[mid], ze)) lo = mid + 1;
+                            else hi = mid;
+                        }
+                        mpos = e + (lo - os);
+                    } else {
+                        const uint32_t ps = sStart[mypart];
+                        if (mypart >= 1) {
+                            const uint32_t s = sStart[mypart - 1];
+                            if (sX[s].x == (xe.x & ~1ull) && sX[s].y == xe.y) {
+                                os = s;
+                                oe = ps;
+                            }
+                        }
+                        uint32_t lo = os, hi = oe;  // partner-group strings with z <= ze
+                        while (lo < hi) {
+                            const uint32_t mid = (lo + hi) >> 1;
+                            if (k_le(sZ[mid], ze)) lo = mid + 1;
+                            else hi = mid;
+                        }
+                        mpos = e - (oe - os) + (lo - os);
+                    }
+                    if (mpos < m) sMidx[mpos] = uint16_t(e);
+                    else atomicOr(&ctrl->err, kErrInternal);
+                }
+            }
+            __syncthreads();
+
+            // ---- emission plan in merged order
+            uint32_t entA[kRxIPT], entB[kRxIPT];
+            uint32_t cntA = 0, cntB = 0;
+#pragma unroll
+            for (int k = 0; k < kRxIPT; ++k) {
+                entA[k] = entB[k] = 0xFFFFFFFFu;
+                const uint32_t q = e0 + k;
+                if (q >= m) continue;
+                const uint32_t e = sMidx[q];
+                if (!sAlive[e]) continue;
+                const ulonglong2 xe = sX[e], ze = sZ[e];
+                const bool isB = xe.x & 1ull;
+                const bool ac = ((zw == 0 ? ze.x : ze.y) & zmask) != 0ull;
+                if (!isB) {
+                    uint32_t e2 = 0xFFFFu;
+                    if (q + 1 < m) {
+                        const uint32_t c = sMidx[q + 1];
+                        if (sX[c].x == (xe.x | 1ull) && sX[c].y == xe.y && k_eq(sZ[c], ze) && sAlive[c]) e2 = c;
+                    }
+                    if (e2 != 0xFFFFu) {
+                        entA[k] = out_entry(e, e2, ac ? 3u : 0u);
+                        entB[k] = out_entry(e2, e, ac ? 3u : 0u);
+                    } else if (ac) {
+                        if (g.any_c) entA[k] = out_entry(e, 0, 1u);
+                        if (g.any_s) entB[k] = out_entry(e, 0, 2u);
+                    } else {
+                        entA[k] = out_entry(e, 0, 0u);
+                    }
+                } else {
+                    bool paired = false;
+                    if (q > 0) {
+                        const uint32_t c = sMidx[q - 1];
+                        paired = sX[c].x == (xe.x & ~1ull) && sX[c].y == xe.y && k_eq(sZ[c], ze) && sAlive[c];
+                    }
+                    if (paired) {
+                        // emitted by the A string of the pair
+                    } else if (ac) {
+                        if (g.any_s) entA[k] = out_entry(e, 0, 2u);
+                        if (g.any_c) entB[k] = out_entry(e, 0, 1u);
+                    } else {
+                        entB[k] = out_entry(e, 0, 0u);
+                    }
+                }
+                cntA += entA[k] != 0xFFFFFFFFu;
+                cntB += entB[k] != 0xFFFFFFFFu;
+            }
+            uint32_t totPacked;
+            const uint32_t offPacked = block_excl_scan(cntA | (cntB << 16), sWave, totPacked);
+            totA = totPacked & 0xFFFFu;
+            totB = totPacked >> 16;
+            {
+                uint32_t oa = offPacked & 0xFFFFu, ob = offPacked >> 16;
+#pragma unroll
+                for (int k = 0; k < kRxIPT; ++k) {
+                    if (entA[k] != 0xFFFFFFFFu) sOut[0][oa++] = entA[k];
+                    if (entB[k] != 0xFFFFFFFFu) sOut[1][ob++] = entB[k];
+                }
+            }
+
+            // ---- publish this tile's output counts
+            if (wave < 2) lb2_publish(st, gst, tile, ep, wave ? totB : totA, &ctrl->err);
         }
 
-        // ---- tile bases: wave 0 front run, wave 1 back run
-        if (wave < 2) {  // wave 0: front run, wave 1: back run (two-level look-back)
-            const uint64_t gmax = A.max_tiles / 64 + 2;
-            uint64_t* st = A.status + wave * A.max_tiles;
-            uint64_t* gst = A.status + 2 * A.max_tiles + wave * gmax;
-            const uint64_t b = lookback_wave2(st, gst, tile, ep, wave ? totB : totA, &ctrl->err);
+        // ---- offsets of the held tile (waves 0 and 1)
+        if (wave < 2 && h_tile != kNoTile) {
+            const uint64_t b = lb2_resolve(st, gst, h_tile, ep, wave ? h_totB : h_totA, &ctrl->err);
             if (lane_id() == 0) sBase[wave] = b;
         }
         __syncthreads();
-        const uint64_t baseA = sBase[0], baseB = sBase[1];
-        if (tile == ntiles - 1 && tid == 0) {
-            const uint64_t tf = baseA + totA, tb = baseB + totB;
-            if (tf + tb > cap) {
-                atomicOr(&ctrl->err, kErrCapacity);
-                atomicMax(reinterpret_cast<unsigned long long*>(&ctrl->need),
-                          static_cast<unsigned long long>(tf + tb));
-            } else {
-                ctrl->nf[A.out_buf] = tf;
-                ctrl->nb[A.out_buf] = tb;
+        // ---- write the held tile at the bases in sBase
+        if (h_tile != kNoTile) {
+            const uint64_t bA = sBase[0], bB = sBase[1];
+            if (h_tile == ntiles - 1 && tid == 0) {
+                const uint64_t tf = bA + h_totA, tb = bB + h_totB;
+                if (tf + tb > cap) {
+                    atomicOr(&ctrl->err, kErrCapacity);
+                    atomicMax(reinterpret_cast<unsigned long long*>(&ctrl->need),
+                              static_cast<unsigned long long>(tf + tb));
+                } else {
+                    ctrl->nf[A.out_buf] = tf;
+                    ctrl->nb[A.out_buf] = tb;
+                }
             }
-        }
-
-        // ---- coalesced writes of the front and back runs
-#pragma unroll 1
-        for (int side = 0; side < 2; ++side) {
-            const uint32_t tot = side ? totB : totA;
-            const uint64_t base = side ? baseB : baseA;
-            for (uint32_t i = tid; i < tot; i += kThreads) {
-                const uint32_t en = sOut[side][i];
-                const uint32_t e = en & 0x3FFu, e2 = (en >> 10) & 0x3FFu, kind = en >> 20;
-                const ulonglong2 xe = sX[e];
-                const ulonglong2 xo = rotr1_n(make_ulonglong2(side ? (xe.x | 1ull) : (xe.x & ~1ull), xe.y), A.nq);
-                const uint64_t o = base + i;
+#pragma unroll
+            for (int k = 0; k < KR; ++k) {
+                const uint32_t j = uint32_t(k) * kThreads + tid;
+                if (j >= h_totA + h_totB) continue;
+                const bool side = j >= h_totA;
+                const uint64_t o = side ? bB + (j - h_totA) : bA + j;
                 if (o >= cap) continue;
                 const uint64_t po = side ? cap - 1 - o : o;
-                A.Xout[po] = xo;
-                A.Zout[po] = sZ[e];
-                const bool neg = side == 0;
+                A.Xout[po] = make_ulonglong2(hxl[k], hxh[k]);
+                A.Zout[po] = make_ulonglong2(hzl[k], hzh[k]);
                 CT* dst = Cout + po * LP;
-                const CT* ce = kStageC ? (sC + e * LP) : (Cin + rx_phys(T, e, nf, cap) * LP);
-                const CT* ce2 = kStageC ? (sC + e2 * LP) : (Cin + rx_phys(T, e2, nf, cap) * LP);
+                if constexpr (kStageC) {
 #pragma unroll
-                for (int a = 0; a < LP; ++a) {
-                    CT v;
-                    if (kind == 0) v = ce[a];
-                    else if (kind == 1) v = Arith<CT>::scale_c(g, a, ce[a]);
-                    else if (kind == 2) v = Arith<CT>::scale_s(g, a, ce[a], neg);
-                    else v = Arith<CT>::pair(g, a, ce[a], ce2[a], neg);
-                    dst[a] = v;
-                    vmax[a] = fmax(vmax[a], absd(v));
+                    for (int a = 0; a < LP; ++a) dst[a] = hc[k][a];
+                } else {
+                    const uint32_t kind = hk[k] & 3u;
+                    const bool neg = (hk[k] >> 2) == 0u;
+                    const CT* ce = Cin + hp1[k] * LP;
+                    const CT* ce2 = Cin + hp2[k] * LP;
+#pragma unroll
+                    for (int a = 0; a < LP; ++a) {
+                        const CT v = rx_value<CT, LP>(g, a, kind, neg, ce[a], kind == 3 ? ce2[a] : CT(0));
+                        dst[a] = v;
+                        vmax[a] = fmax(vmax[a], absd(v));
+                    }
                 }
             }
         }
-        __syncthreads();
+
+        if (!have) {
+            h_tile = kNoTile;
+        } else if (totA + totB <= uint32_t(KR * kThreads)) {
+            // ---- gather this tile's outputs into registers
+#pragma unroll
+            for (int k = 0; k < KR; ++k) {
+                const uint32_t j = uint32_t(k) * kThreads + tid;
+                if (j >= totA + totB) continue;
+                const bool side = j >= totA;
+                const uint32_t en = sOut[side][side ? j - totA : j];
+                const uint32_t e = en & 0x3FFu, e2 = (en >> 10) & 0x3FFu, kind = en >> 20;
+                const ulonglong2 xe = sX[e], ze = sZ[e];
+                const ulonglong2 xo = rotr1_n(make_ulonglong2(side ? (xe.x | 1ull) : (xe.x & ~1ull), xe.y), A.nq);
+                hxl[k] = xo.x;
+                hxh[k] = xo.y;
+                hzl[k] = ze.x;
+                hzh[k] = ze.y;
+                if constexpr (kStageC) {
+#pragma unroll
+                    for (int a = 0; a < LP; ++a) {
+                        const CT v = rx_value<CT, LP>(g, a, kind, !side, sC[e * LP + a], sC[e2 * LP + a]);
+                        hc[k][a] = v;
+                        vmax[a] = fmax(vmax[a], absd(v));
+                    }
+                } else {
+                    hp1[k] = rx_phys(T, e, nf, cap);
+                    hp2[k] = rx_phys(T, e2, nf, cap);
+                    hk[k] = kind | (uint32_t(side) << 2);
+                }
+            }
+            h_tile = tile;
+            h_totA = totA;
+            h_totB = totB;
+        } else {
+            // ---- too many outputs to hold: resolve and write this tile now
+            __syncthreads();  // every thread has read sBase
+            if (wave < 2) {
+                const uint64_t b = lb2_resolve(st, gst, tile, ep, wave ? totB : totA, &ctrl->err);
+                if (lane_id() == 0) sBase[wave] = b;
+            }
+            __syncthreads();
+            const uint64_t baseA = sBase[0], baseB = sBase[1];
+            if (tile == ntiles - 1 && tid == 0) {
+                const uint64_t tf = baseA + totA, tb = baseB + totB;
+                if (tf + tb > cap) {
+                    atomicOr(&ctrl->err, kErrCapacity);
+                    atomicMax(reinterpret_cast<unsigned long long*>(&ctrl->need),
+                              static_cast<unsigned long long>(tf + tb));
+                } else {
+                    ctrl->nf[A.out_buf] = tf;
+                    ctrl->nb[A.out_buf] = tb;
+                }
+            }
+#pragma unroll 1
+            for (int side = 0; side < 2; ++side) {
+                const uint32_t tot = side ? totB : totA;
+                const uint64_t base = side ? baseB : baseA;
+                for (uint32_t i = tid; i < tot; i += kThreads) {
+                    const uint32_t en = sOut[side][i];
+                    const uint32_t e = en & 0x3FFu, e2 = (en >> 10) & 0x3FFu, kind = en >> 20;
+                    const ulonglong2 xe = sX[e];
+                    const ulonglong2 xo =
+                        rotr1_n(make_ulonglong2(side ? (xe.x | 1ull) : (xe.x & ~1ull), xe.y), A.nq);
+                    const uint64_t o = base + i;
+                    if (o >= cap) continue;
+                    const uint64_t po = side ? cap - 1 - o : o;
+                    A.Xout[po] = xo;
+                    A.Zout[po] = sZ[e];
+                    CT* dst = Cout + po * LP;
+                    const CT* ce = kStageC ? (sC + e * LP) : (Cin + rx_phys(T, e, nf, cap) * LP);
+                    const CT* ce2 = kStageC ? (sC + e2 * LP) : (Cin + rx_phys(T, e2, nf, cap) * LP);
+#pragma unroll
+                    for (int a = 0; a < LP; ++a) {
+                        const CT v = rx_value<CT, LP>(g, a, kind, side == 0, ce[a], kind == 3 ? ce2[a] : CT(0));
+                        dst[a] = v;
+                        vmax[a] = fmax(vmax[a], absd(v));
+                    }
+                }
+            }
+            h_tile = kNoTile;
+        }
+        // the next tile (acquire_tile's barrier also frees this tile's LDS)
+        tile = have ? acquire_tile(ctrl, &sTile) : kNoTile;
     }
 
     // ---- per-lane max of the outputs
@@ -464,6 +588,19 @@ __global__ __launch_bounds__(kThreads) void k_rx_merge(RxArgs A, GateTrig g) {
             ctrl->cnt_rx_launches += 1;
         }
     }
+}
+
+// Rows of one coefficient (or two binary32 lanes): outputs held in registers,
+// four workgroups per CU (LDS allows four; the register budget is held to it).
+template <typename CT, int LP>
+__global__ __launch_bounds__(kThreads, 4) void k_rx_merge(RxArgs A, GateTrig g) {
+    rx_merge_body<CT, LP, kRxHold>(A, g);
+}
+
+// Wider rows: every tile written as soon as its offsets are known.
+template <typename CT, int LP>
+__global__ __launch_bounds__(kThreads) void k_rx_merge_wide(RxArgs A, GateTrig g) {
+    rx_merge_body<CT, LP, 0>(A, g);
 }
 
 // ================================================================ Clifford pass / compaction
@@ -763,6 +900,10 @@ __global__ __launch_bounds__(kThreads) void k_sort_pass(SortPassArgs A) {
             A.Xd[o] = A.Xs[i];
 #pragma unroll
             for (int a = 0; a < LP; ++a) Cd[o * LP + a] = Cs[i * LP + a];
+            if (A.Ls) {
+#pragma unroll
+                for (int a = 0; a < LP; ++a) A.Ld[o * LP + a] = A.Ls[i * LP + a];
+            }
         }
         __syncthreads();
     }
@@ -853,12 +994,18 @@ __global__ void k_fill_u64(uint64_t* p, uint64_t v, size_t n) {
 // ================================================================ launchers
 
 hipError_t launch_rx_partition(const RxArgs& a, hipStream_t s) {
-    k_rx_partition<<<dim3(256), dim3(kThreads), 0, s>>>(a.ctrl, a.in_buf, a.Xin, a.Zin, a.cap, a.desc);
+    k_rx_partition<<<dim3(1024), dim3(kThreads), 0, s>>>(a.ctrl, a.in_buf, a.Xin, a.Zin, a.cap, a.desc);
     return hipGetLastError();
 }
 
 hipError_t launch_rx(const RxArgs& a, const GateTrig& g, int dtype, int lp, hipStream_t s, int grid) {
-#define L_RX(T, L) k_rx_merge<T, L><<<dim3(grid), dim3(kThreads), 0, s>>>(a, g)
+    if (lp * (dtype == 0 ? 8 : 4) <= 8) {
+        if (dtype == 0) k_rx_merge<double, 1><<<dim3(grid), dim3(kThreads), 0, s>>>(a, g);
+        else if (lp == 1) k_rx_merge<float, 1><<<dim3(grid), dim3(kThreads), 0, s>>>(a, g);
+        else k_rx_merge<float, 2><<<dim3(grid), dim3(kThreads), 0, s>>>(a, g);
+        return hipGetLastError();
+    }
+#define L_RX(T, L) k_rx_merge_wide<T, L><<<dim3(grid), dim3(kThreads), 0, s>>>(a, g)
     ORQA_DISPATCH(dtype, lp, L_RX);
 #undef L_RX
     return hipGetLastError();
@@ -981,6 +1128,10 @@ __global__ __launch_bounds__(kGsThreads) void k_group_sort(GroupSortArgs A) {
             const uint64_t d = a + gs + r;
             A.Xd[d] = xr[k];
             A.Zd[d] = z;
+            if (A.Ls) {
+#pragma unroll
+                for (int l = 0; l < LP; ++l) A.Ld[d * LP + l] = A.Ls[(a + e) * LP + l];
+            }
             if constexpr (kRegC) {
 #pragma unroll
                 for (int l = 0; l < LP; ++l) Cd[d * LP + l] = cr[k][l];

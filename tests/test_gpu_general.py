@@ -281,3 +281,34 @@ def test_general_gate_with_x_letters_inside_an_rx_run_keeps_the_stream():
     say(f"stream across a general gate: rx launches {st['rx_launches']:.0f}, run merges {st['run_merges']:.0f}")
     assert st["rx_launches"] == 4 and st["run_merges"] == 1
     assert_same_operator(g, o, coeff_exact=True)
+
+
+@pytest.mark.parametrize("which", ["xy_weight2", "rx_out_of_order", "z_only_non_clifford", "weight3_lanes4"])
+def test_fp32_general_gate_within_one_ulp_of_oracle(which):
+    """Binary32 general gates are compensated like the RX merge: the branch
+    keeps each product exact as a rounded head plus a low word, and the
+    equal-key pass sums the (at most two) pairs of a key with two-sum and
+    rounds once.  One gate on a random set whose coefficients are binary32
+    values: every output is within one binary32 ulp of the oracle's binary64
+    value rounded to binary32 (Eq. update_rule), for the in-group sort
+    (Z-only generator), the run merge (few flipped bits) and the radix sort
+    (weight 3 with lanes)."""
+    n = 20
+    lanes = 4 if which == "weight3_lanes4" else 1
+    terms, coeffs = w.random_pauli_set(n, 4000, seed=7, support=list(range(10)), lanes=lanes)
+    coeffs = coeffs.astype(np.float32).astype(np.float64)
+    letters = {"xy_weight2": {1: "X", 4: "Y"}, "rx_out_of_order": {3: "X"},
+               "z_only_non_clifford": {2: "Z", 5: "Z"}, "weight3_lanes4": {0: "Y", 2: "Y", 7: "X"}}[which]
+    th = np.array([[0.7, -1.1, 2.3, 0.4][:lanes]])
+    gate = w.GateList(w.pauli_words(n, letters)[None, :], th)
+    g32 = gpu_sum(n, terms, coeffs, dtype=1).apply_rotation_layer(gate)
+    o = OracleSum(n, terms, coeffs).apply(gate)
+    k32, c32 = g32.export()
+    ok, oc = o.export()
+    assert np.array_equal(k32, ok)
+    ref = oc.astype(np.float32)
+    diff = np.abs(c32.astype(np.float64) - ref.astype(np.float64))
+    ulp = np.spacing(np.abs(ref)).astype(np.float64)
+    say(f"{which}: {k32.shape[0]} strings, exact {np.mean(diff == 0):.4f}, max diff / ulp "
+        f"{np.max(diff / np.maximum(ulp, 1e-300)):.3f}")
+    assert np.all(diff <= ulp)

@@ -79,3 +79,29 @@ def test_graphs_off_again_and_timing_bypass():
         _same(e, g)
     st = g.stats()
     assert st["graph_captures"] + st["graph_replays"] >= 2
+
+
+def test_graph_replays_equal_oracle_127q():
+    """The benchmark workload (127 q, theta_h = 0.8, eps0 = 1e-4, binary64)
+    with every RX run replayed from a graph once captured: keys and
+    coefficients equal the oracle's bit for bit after every step (Eq.
+    update_rule, Eq. truncation1), with at least one replay among the steps."""
+    from oracle import OracleSum
+    from gpu_common import assert_same_operator
+
+    lat = w.eagle_127()
+    zz, rx = w.kicked_ising_step(lat, 0.8)
+    terms, coef = w.single_pauli_term(lat.n, {62: "Z"})
+    # capacity for the whole run: no growth, so the buffers (part of a
+    # graph's key) stay put and later steps replay
+    g = gpu_sum(lat.n, terms, coef, capacity=1 << 22).set_graphs(True)
+    o = OracleSum(lat.n, terms, coef)
+    for t in range(5):
+        g.apply_rotation_layer(zz, 1e-4).apply_rotation_layer(rx, 1e-4)
+        o.apply(zz, 1e-4).apply(rx, 1e-4)
+        assert_same_operator(g, o, coeff_exact=True)
+        assert abs(g.expectation_z()[0] - o.expectation_z()[0]) <= 1e-12
+        say(f"graph vs oracle step {t + 1}: |O| = {g.size()}")
+    st = g.stats()
+    say(f"graphs: {st['graph_captures']} captures, {st['graph_replays']} replays")
+    assert st["graph_replays"] >= 1
