@@ -261,6 +261,16 @@ int pauli_sum_set_graphs(ps_handle* h, int enable);
 int pauli_sum_set_lookback_epoch(ps_handle* h, uint32_t epoch);
 int pauli_sum_lookback_epoch(ps_handle* h, uint32_t* epoch);
 
+/*
+ * RX tile boundaries (for tests of both paths).  The streaming pass of a
+ * sigma_x rotation (Eq. update_rule) cuts its merged order into tiles; the
+ * grid first finds every tile boundary (each stored as words tagged with the
+ * launch's epoch), and a tile whose boundaries have not arrived in time
+ * finds them itself.  enable == 0 skips the first step, so that every tile
+ * finds its own boundaries; results are identical either way.
+ */
+int pauli_sum_set_rx_boundary_prologue(ps_handle* h, int enable);
+
 typedef struct ps_scorer ps_scorer;
 int ps_scorer_create(int n_qubits, const uint64_t* qmask, const uint8_t* letters, const float* scales,
                      void* hip_stream, ps_scorer** out);

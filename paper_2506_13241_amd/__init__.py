@@ -28,7 +28,7 @@ EXPORTED_SYMBOLS = (
     "ps_scorer_create", "ps_scorer_destroy", "ps_scorer_set_params", "ps_scorer_get_params", "ps_scorer_set_data",
     "ps_scorer_forward", "ps_scorer_loss_grad", "ps_scorer_adam_step", "pauli_sum_set_graphs",
     "pauli_sum_histogram", "pauli_sum_set_sort_config", "pauli_sum_histogram_noalloc",
-    "pauli_sum_set_lookback_epoch", "pauli_sum_lookback_epoch",
+    "pauli_sum_set_lookback_epoch", "pauli_sum_lookback_epoch", "pauli_sum_set_rx_boundary_prologue",
 )
 N_SCORER_PARAMS = 37249
 SORT_CONFIGS = ((8, 8), (8, 16), (7, 16), (6, 16), (7, 8), (6, 8))  # (digit bits, items per thread)
@@ -89,6 +89,7 @@ def load_library(path: str = LIB_PATH):
         "pauli_sum_histogram": (I, [P, I, P, I, I, P]),
         "pauli_sum_histogram_noalloc": (I, [P, I, P, I, I, P]),
         "pauli_sum_set_lookback_epoch": (I, [P, ctypes.c_uint32]),
+        "pauli_sum_set_rx_boundary_prologue": (I, [P, I]),
         "pauli_sum_lookback_epoch": (I, [P, ctypes.POINTER(ctypes.c_uint32)]),
         "pauli_sum_set_sort_config": (I, [P, I, I]),
         "ps_scorer_create": (I, [I, P, P, P, P, ctypes.POINTER(P)]),
@@ -238,6 +239,11 @@ class PauliSum:
         _check(f(self._h, lane, _ptr(e), e.size - 1, int(signed), _ptr(out)))
         return out
 
+    def set_rx_boundary_prologue(self, enable: bool = True):
+        """enable=False: every RX tile finds its own boundaries (tests of that path)."""
+        _check(_lib.pauli_sum_set_rx_boundary_prologue(self._h, int(enable)))
+        return self
+
     def set_lookback_epoch(self, epoch: int):
         """Clear the look-back status words and restart their epoch (tests of the wrap guard)."""
         _check(_lib.pauli_sum_set_lookback_epoch(self._h, int(epoch)))
@@ -367,6 +373,10 @@ def pauli_sum_set_lookback_epoch(ps: PauliSum, epoch: int):
 
 def pauli_sum_lookback_epoch(ps: PauliSum) -> int:
     return ps.lookback_epoch()
+
+
+def pauli_sum_set_rx_boundary_prologue(ps: PauliSum, enable: bool = True):
+    return ps.set_rx_boundary_prologue(enable)
 
 
 def pauli_sum_load_scorer(ps: PauliSum, scorer: PsScorer):

@@ -126,7 +126,8 @@ struct ps_handle {
     Buf buf[2] = {};
     uint32_t* rank[2] = {nullptr, nullptr};
     Ctrl* ctrl = nullptr;
-    TileDesc* desc = nullptr;
+    TileDesc* desc = nullptr;  // RX tile boundaries (written and read by each RX launch)
+    size_t desc_words = 0;     // desc as 64-bit words (each tagged with a launch epoch)
     uint64_t* status = nullptr;
     size_t status_words = 0;
     uint64_t max_tiles = 0;
@@ -141,6 +142,8 @@ struct ps_handle {
     int xrot = 0;       // stored x = x rotated right by xrot
     hipStream_t stream = nullptr;
     int grid = 1024;
+    int rx_grid = 1024;  // RX merge workgroups: what the CUs hold at once (at most grid)
+    bool rx_no_prologue = false;  // tiles find their own boundaries (pauli_sum_set_rx_boundary_prologue)
     size_t gates_applied = 0;
     uint64_t n_host = 0;  // size after the last synchronisation
     bool broken = false;
@@ -203,6 +206,7 @@ size_t coef_bytes(const ps_handle* h) { return h->csize; }
 struct Aux {
     uint32_t* rank[2] = {nullptr, nullptr};
     TileDesc* desc = nullptr;
+    size_t desc_words = 0;
     uint64_t* status = nullptr;
     size_t status_words = 0;
     uint64_t max_tiles = 0;
@@ -260,11 +264,13 @@ bool alloc_aux(ps_handle* h, size_t cap, bool with_score, Aux* a) {
              grab(reinterpret_cast<void**>(&a->lo[1]), cap * h->LP * sizeof(float));
     // status words start from a zero epoch tag the kernels never use (epoch starts at 1)
     if (ok) ok = hipMemsetAsync(a->status, 0, words * sizeof(uint64_t), h->stream) == hipSuccess;
+    if (ok) ok = hipMemsetAsync(a->desc, 0, (mt + 2) * sizeof(TileDesc), h->stream) == hipSuccess;
     if (!ok) {
         free_aux(a);
         return false;
     }
     a->status_words = words;
+    a->desc_words = (mt + 2) * sizeof(TileDesc) / sizeof(uint64_t);
     a->max_tiles = std::max(mt, st_tiles);
     return true;
 }
@@ -274,6 +280,7 @@ Aux take_aux(ps_handle* h) {
     a.rank[0] = h->rank[0];
     a.rank[1] = h->rank[1];
     a.desc = h->desc;
+    a.desc_words = h->desc_words;
     a.status = h->status;
     a.status_words = h->status_words;
     a.max_tiles = h->max_tiles;
@@ -292,6 +299,7 @@ void put_aux(ps_handle* h, const Aux& a) {
     h->rank[0] = a.rank[0];
     h->rank[1] = a.rank[1];
     h->desc = a.desc;
+    h->desc_words = a.desc_words;
     h->status = a.status;
     h->status_words = a.status_words;
     h->max_tiles = a.max_tiles;
@@ -475,6 +483,7 @@ int lb_reserve(ps_handle* h, uint64_t k) {
     }
     HIP_TRY(hipStreamSynchronize(h->stream));
     HIP_TRY(launch_fill_u64(h->status, 0ull, h->status_words, h->stream));
+    HIP_TRY(launch_fill_u64(reinterpret_cast<uint64_t*>(h->desc), 0ull, h->desc_words, h->stream));
     const uint32_t one = 1;
     HIP_TRY(hipMemcpyAsync(&h->ctrl->epoch, &one, sizeof one, hipMemcpyHostToDevice, h->stream));
     HIP_TRY(hipStreamSynchronize(h->stream));
@@ -565,14 +574,14 @@ int enqueue_rx(ps_handle* h, int in, int out, int mx_in, int mx_out, double eps_
     a.max_tiles = h->max_tiles;
     a.eps_in = eps_in;
     a.nq = h->nq;
+    a.no_prologue = h->rx_no_prologue ? 1 : 0;
     if (!capturing) LB_RESERVE(h, 1);  // a captured run reserves its launches at replay
-    HIP_TRY(launch_rx_partition(a, stream));
     size_t slot = SIZE_MAX;
     if (timed) {
         int rc = ev_begin(h, 0, &slot);
         if (rc) return rc;
     }
-    HIP_TRY(launch_rx(a, g, h->dtype, h->LP, stream, h->grid));
+    HIP_TRY(launch_rx(a, g, h->dtype, h->LP, stream, h->rx_grid));
     return ev_end(h, slot);
 }
 
@@ -1178,6 +1187,8 @@ int pauli_sum_create(int n_qubits, int n_lanes, int dtype, size_t capacity, cons
         h->dev = dev;
         if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
             h->grid = cus * 4;
+        const int per_cu = rx_blocks_per_cu(dtype, h->LP);
+        h->rx_grid = (cus > 0 && per_cu > 0) ? std::min(h->grid, cus * per_cu) : h->grid;
     }
 
     // host-side canonical order: (stored x, z) ascending, duplicates summed
@@ -1841,6 +1852,13 @@ int pauli_sum_set_sort_config(ps_handle* h, int digit_bits, int items_per_thread
                 items_per_thread);
 }
 
+int pauli_sum_set_rx_boundary_prologue(ps_handle* h, int enable) {
+    if (!h) return fail(PS_ERR_INVALID, "handle is NULL");
+    h->rx_no_prologue = enable == 0;
+    drop_graphs(h);  // captured launches carry the setting
+    return PS_OK;
+}
+
 int pauli_sum_set_lookback_epoch(ps_handle* h, uint32_t epoch) {
     if (!h) return fail(PS_ERR_INVALID, "NULL argument");
     if (h->broken) return fail(PS_ERR_DEVICE, "handle is no longer usable");
@@ -1848,6 +1866,7 @@ int pauli_sum_set_lookback_epoch(ps_handle* h, uint32_t epoch) {
         return fail(PS_ERR_INVALID, "epoch must be in 1..%llu", static_cast<unsigned long long>(kEpochLimit - 1));
     HIP_TRY(hipStreamSynchronize(h->stream));
     HIP_TRY(launch_fill_u64(h->status, 0ull, h->status_words, h->stream));
+    HIP_TRY(launch_fill_u64(reinterpret_cast<uint64_t*>(h->desc), 0ull, h->desc_words, h->stream));
     HIP_TRY(hipMemcpyAsync(&h->ctrl->epoch, &epoch, sizeof epoch, hipMemcpyHostToDevice, h->stream));
     HIP_TRY(hipStreamSynchronize(h->stream));
     h->lb_count = epoch - 1;

@@ -96,11 +96,12 @@ struct RxArgs {
     ulonglong2* Zout;
     void* Cout;
     uint64_t cap;
-    TileDesc* desc;    // tile boundaries (k_rx_partition), ntiles + 1
+    TileDesc* desc;    // tile boundaries of the input (found by the kernel itself), ntiles + 1
     uint64_t* status;  // 2 x (max_tiles + max_tiles / 64 + 2): tile words, then group words, per channel
     uint64_t max_tiles;
     double eps_in;     // pending truncation of the input (<= 0: none)
     int nq;
+    int no_prologue;   // tiles find their own boundaries (tests of that path)
 };
 
 struct CompactArgs {
@@ -163,8 +164,8 @@ struct SortPassArgs {
 };
 
 // Host-side launchers (orqa_kernels.hip), dispatching on dtype and padded lanes.
-hipError_t launch_rx_partition(const RxArgs& a, hipStream_t s);
 hipError_t launch_rx(const RxArgs& a, const GateTrig& g, int dtype, int lp, hipStream_t s, int grid);
+int rx_blocks_per_cu(int dtype, int lp);
 hipError_t launch_compact(const CompactArgs& a, int dtype, int lp, hipStream_t s, int grid);
 hipError_t launch_sort_hist(Ctrl* ctrl, int buf, const uint32_t* R, const ulonglong2* Z, const ulonglong2* X,
                             const SortPlan& plan, uint32_t* hist, hipStream_t s, int grid);

@@ -52,20 +52,68 @@ __device__ __forceinline__ uint64_t wave_lower_bound(uint64_t lo, uint64_t hi, P
     return lo;
 }
 
+// The same split by one thread (binary searches; few registers, many
+// dependent loads): the fallback of a tile whose boundaries were not found in
+// time by the grid.
+__device__ uint64_t first_geq_h(const VIn& v, ulonglong2 key, uint64_t lo, uint64_t hi, bool strict) {
+    while (lo < hi) {  // first i in [lo, hi) with h(X[i]) >= key (> key when strict)
+        const uint64_t mid = lo + (hi - lo) / 2;
+        const ulonglong2 h = k_h(v.x(mid));
+        if (strict ? k_le(h, key) : k_lt(h, key)) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+__device__ TileDesc thread_split(const VIn& v, uint64_t n, uint64_t b) {
+    if (b >= n) return {n, n, n, n};
+    const ulonglong2 H = k_h(v.x(b));
+    const uint64_t hs = first_geq_h(v, H, 0, b, false);
+    const uint64_t he = first_geq_h(v, H, b + 1, n, true);
+    uint64_t lo = hs, hi = he;  // first B string: first X >= (H with bit 0 set)
+    const ulonglong2 H1 = make_ulonglong2(H.x | 1ull, H.y);
+    while (lo < hi) {
+        const uint64_t mid = lo + (hi - lo) / 2;
+        if (k_lt(v.x(mid), H1)) lo = mid + 1;
+        else hi = mid;
+    }
+    const uint64_t hm = lo, na = hm - hs, nbb = he - hm, d = b - hs;
+    uint64_t ilo = d > nbb ? d - nbb : 0, ihi = d < na ? d : na;
+    while (ilo < ihi) {
+        const uint64_t mid = ilo + (ihi - ilo) / 2;
+        if (k_le(v.z(hs + mid), v.z(hm + d - 1 - mid))) ilo = mid + 1;
+        else ihi = mid;
+    }
+    uint64_t k = d - ilo;
+    if (ilo > 0 && k < nbb && k_eq(v.z(hs + ilo - 1), v.z(hm + k))) k += 1;
+    return {hs + ilo, hm + k, hm, he};
+}
+
+__device__ __forceinline__ ulonglong2 shfl_u128(const ulonglong2& v, int src) {
+    const uint32_t a = __shfl(static_cast<uint32_t>(v.x), src, 64);
+    const uint32_t b = __shfl(static_cast<uint32_t>(v.x >> 32), src, 64);
+    const uint32_t c = __shfl(static_cast<uint32_t>(v.y), src, 64);
+    const uint32_t d = __shfl(static_cast<uint32_t>(v.y >> 32), src, 64);
+    return make_ulonglong2((uint64_t(b) << 32) | a, (uint64_t(d) << 32) | c);
+}
+
 // Split of merged position b (all 64 lanes, uniform result): the input
 // positions where it falls in the A and B groups of its pairing block, the
 // block's first B position and its end.  One window of 128 keys around b
-// usually settles the block; wider blocks take 64-ary searches.
+// (one round trip to memory) settles any block that lies inside it, the
+// merge path included; wider blocks take 64-ary searches.
 __device__ TileDesc wave_split(const VIn& v, uint64_t n, uint64_t b) {
     if (b >= n) return {n, n, n, n};
     const int lane = lane_id();
-    const ulonglong2 H = k_h(v.x(b));
-    const ulonglong2 H1 = make_ulonglong2(H.x | 1ull, H.y);
-    // lane l reads positions b - 64 + l and b + l
+    // lane l reads positions b - 64 + l and b + l (lane 0's second key is b)
     const int64_t pb = int64_t(b) - 64 + lane;
     const uint64_t pf = b + uint64_t(lane);
     const ulonglong2 xb = pb >= 0 ? v.x(uint64_t(pb)) : make_ulonglong2(0, 0);
     const ulonglong2 xf = pf < n ? v.x(pf) : make_ulonglong2(0, 0);
+    const ulonglong2 zb = pb >= 0 ? v.z(uint64_t(pb)) : make_ulonglong2(0, 0);
+    const ulonglong2 zf = pf < n ? v.z(pf) : make_ulonglong2(0, 0);
+    const ulonglong2 H = k_h(shfl_u128(xf, 0));
+    const ulonglong2 H1 = make_ulonglong2(H.x | 1ull, H.y);
     // block start: h is non-decreasing, so the lanes before the block form a prefix
     const uint64_t before = __ballot(pb < 0 || k_lt(k_h(xb), H));
     const uint64_t hs = before != 0
@@ -89,28 +137,101 @@ __device__ TileDesc wave_split(const VIn& v, uint64_t n, uint64_t b) {
     const uint64_t na = hm - hs, nbb = he - hm, d = b - hs;
     // merge path: i = number of A strings among the first d merged
     const uint64_t ilo = d > nbb ? d - nbb : 0, ihi = d < na ? d : na;
-    const uint64_t i = wave_lower_bound(
-        ilo, ihi, [&](uint64_t mid) { return !k_le(v.z(hs + mid), v.z(hm + d - 1 - mid)); });
-    uint64_t k = d - i;
-    if (i > 0 && k < nbb && k_eq(v.z(hs + i - 1), v.z(hm + k))) k += 1;  // keep the pair together
+    uint64_t i;
+    ulonglong2 za, zk;  // z of A string i - 1 and of B string k (the pair check)
+    uint64_t k;
+    if (before != 0 && after != 0) {
+        // the whole block is in the window: z of position p from the lane
+        // that read it (ihi - ilo <= d <= 64, so one probe per lane)
+        auto zwin = [&](uint64_t p) {
+            const bool back = p < b;
+            const int src = back ? int(int64_t(p) - (int64_t(b) - 64)) : int(p - b);
+            const ulonglong2 u = shfl_u128(zb, src), w2 = shfl_u128(zf, src);
+            return back ? u : w2;
+        };
+        const uint64_t mid = ilo + uint64_t(lane);
+        const uint64_t pa = hs + (mid < ihi ? mid : ilo);
+        const uint64_t pq = hm + d - 1 - (mid < ihi ? mid : ilo);
+        const ulonglong2 zA = zwin(pa < he ? pa : hs), zB = zwin(pq < he ? pq : hs);
+        const uint64_t bal = __ballot(mid < ihi && !k_le(zA, zB));
+        i = (ilo < ihi && bal != 0) ? ilo + uint64_t(__ffsll(static_cast<unsigned long long>(bal)) - 1) : ihi;
+        k = d - i;
+        const uint64_t p1 = i > 0 ? hs + i - 1 : hs, p2 = hm + k < he ? hm + k : hs;
+        za = zwin(p1);
+        zk = zwin(p2);
+    } else {
+        i = wave_lower_bound(ilo, ihi,
+                             [&](uint64_t m) { return !k_le(v.z(hs + m), v.z(hm + d - 1 - m)); });
+        k = d - i;
+        za = v.z(i > 0 ? hs + i - 1 : hs);
+        zk = v.z(hm + k < he ? hm + k : hs);
+    }
+    if (i > 0 && k < nbb && k_eq(za, zk)) k += 1;  // keep the pair together
     return {hs + i, hm + k, hm, he};
 }
 
-// One wave per tile boundary: desc[t] = split of merged position t kRxTile for
-// t = 0 .. ntiles (the last one at n).
-__global__ __launch_bounds__(kThreads) void k_rx_partition(const Ctrl* __restrict__ ctrl, int in_buf,
-                                                           const ulonglong2* __restrict__ X,
-                                                           const ulonglong2* __restrict__ Z, uint64_t cap,
-                                                           TileDesc* __restrict__ desc) {
-    if (ctrl->err) return;
-    const uint64_t nf = ctrl->nf[in_buf], n = nf + ctrl->nb[in_buf];
+// Tile boundaries of an RX gate's input, found by the merge kernel itself
+// before it takes tiles: wave w of the grid finds boundaries w, w + W, ...
+// (W waves), the split of merged position t kRxTile for t = 0 .. ntiles (the
+// last one at n).  Each of its four words is stored as a status word of the
+// launch's epoch, so a tile reads its two boundaries as soon as they are
+// there, with no fence and no grid-wide wait.
+struct TileDescWords {
+    uint64_t w[4];  // posA, posB, hm, he, each tagged like a look-back status word
+};
+
+__device__ __forceinline__ void rx_boundaries(const VIn& v, uint64_t n, TileDescWords* desc, uint32_t ep) {
     const uint64_t ntiles = (n + kRxTile - 1) / kRxTile;
-    const VIn v{X, Z, nf, cap};
     const uint64_t waves = uint64_t(gridDim.x) * (kThreads / 64);
     for (uint64_t t = blockIdx.x * uint64_t(kThreads / 64) + (threadIdx.x >> 6); t <= ntiles; t += waves) {
         const uint64_t b = t * kRxTile;
         const TileDesc d = wave_split(v, n, b < n ? b : n);
-        if (lane_id() == 0) desc[t] = d;
+        const int lane = lane_id();
+        if (lane < 4) {
+            const uint64_t val = lane == 0 ? d.posA : lane == 1 ? d.posB : lane == 2 ? d.hm : d.he;
+            st_rel(&desc[t].w[lane], st_pack(ep, 2, val));
+        }
+    }
+}
+
+// The boundaries of tiles t and t + 1 (uniform), read by wave 0 once all
+// eight words carry this launch's epoch and handed to the workgroup through
+// s_desc (two entries of LDS).  Boundaries that have not arrived after
+// kDescWaitTicks are found by the workgroup itself (waves 0 and 1) and
+// published: a tile never depends on a workgroup that is not running yet.
+constexpr uint64_t kDescWaitTicks = 3000;  // 30 us of the 100 MHz wall clock
+
+__device__ __forceinline__ void rx_read_boundaries(const VIn& v, uint64_t n, TileDescWords* desc, uint64_t t,
+                                                   uint32_t ep, TileDesc* s_desc, uint32_t* s_flag) {
+    if ((threadIdx.x >> 6) == 0) {
+        const int lane = lane_id();
+        const uint64_t t0 = wall_clock64();
+        uint64_t w = 0;
+        bool ready = false;
+        while (true) {
+            if (lane < 8) w = ld_acq(&desc[t + (lane >> 2)].w[lane & 3]);
+            if (!__any(lane < 8 && st_flag(w, ep) != 2u)) {
+                ready = true;
+                break;
+            }
+            if (__any(wall_clock64() - t0 > kDescWaitTicks)) break;
+            __builtin_amdgcn_s_sleep(kLb2Sleep);
+        }
+        if (lane < 8) reinterpret_cast<uint64_t*>(s_desc)[lane] = w & kValMask;
+        if (lane == 0) *s_flag = ready ? 1u : 0u;
+    }
+    __syncthreads();
+    if (*s_flag == 0u) {
+        if (threadIdx.x < 2) {
+            const uint64_t b = (t + threadIdx.x) * kRxTile;
+            const TileDesc d = thread_split(v, n, b < n ? b : n);
+            s_desc[threadIdx.x] = d;
+            st_rel(&desc[t + threadIdx.x].w[0], st_pack(ep, 2, d.posA));
+            st_rel(&desc[t + threadIdx.x].w[1], st_pack(ep, 2, d.posB));
+            st_rel(&desc[t + threadIdx.x].w[2], st_pack(ep, 2, d.hm));
+            st_rel(&desc[t + threadIdx.x].w[3], st_pack(ep, 2, d.he));
+        }
+        __syncthreads();
     }
 }
 
@@ -206,6 +327,7 @@ __device__ __forceinline__ void rx_merge_body(const RxArgs& A, const GateTrig& g
     __shared__ uint32_t sWave[4];
     __shared__ uint32_t sTile;
     __shared__ uint64_t sBase[2];
+    __shared__ TileDesc sDesc[2];  // boundaries of the current tile
     __shared__ double sThr[LP];
 
     Ctrl* ctrl = A.ctrl;
@@ -238,10 +360,15 @@ __device__ __forceinline__ void rx_merge_body(const RxArgs& A, const GateTrig& g
     uint64_t hp1[kStageC ? 1 : KH], hp2[kStageC ? 1 : KH];
     uint32_t hk[kStageC ? 1 : KH];
 
-    // Each iteration takes a tile (while there are tiles: a tile is taken
-    // only when the workgroup is about to load it, so that no tile waits
-    // unpublished behind another tile's look-back), writes the tile held from
-    // the iteration before, and holds the new one.
+    // ---- this gate's tile boundaries, shared out over the grid's waves
+    TileDescWords* const desc = reinterpret_cast<TileDescWords*>(A.desc);
+    if (!skip && !A.no_prologue) rx_boundaries(VIn{A.Xin, A.Zin, nf, cap}, n, desc, ep);
+
+    // Each iteration loads and plans a tile (while there are tiles), writes
+    // the tile held from the iteration before and holds the new one.  A tile
+    // is taken only when the workgroup is about to load it: a tile taken
+    // earlier (e.g. while the held tile's offsets resolve) sits unpublished
+    // behind that wait, and every later tile's look-back waits for it.
     uint32_t tile = acquire_tile(ctrl, &sTile);
     for (;;) {
         const bool have = tile < ntiles;
@@ -249,7 +376,8 @@ __device__ __forceinline__ void rx_merge_body(const RxArgs& A, const GateTrig& g
         RxTile T{};
         uint32_t totA = 0, totB = 0;
         if (have) {
-            T = rx_tile(A.desc[tile], A.desc[tile + 1], n);
+            rx_read_boundaries(VIn{A.Xin, A.Zin, nf, cap}, n, desc, tile, ep, sDesc, &sWave[0]);
+            T = rx_tile(sDesc[0], sDesc[1], n);
             if (!T.sane && tid == 0) atomicOr(&ctrl->err, kErrInternal);
             const uint32_t m = T.m;
 
@@ -993,9 +1121,31 @@ __global__ void k_fill_u64(uint64_t* p, uint64_t v, size_t n) {
 
 // ================================================================ launchers
 
-hipError_t launch_rx_partition(const RxArgs& a, hipStream_t s) {
-    k_rx_partition<<<dim3(1024), dim3(kThreads), 0, s>>>(a.ctrl, a.in_buf, a.Xin, a.Zin, a.cap, a.desc);
-    return hipGetLastError();
+// Workgroups of the RX merge for (dtype, padded lanes) one CU holds at once.
+int rx_blocks_per_cu(int dtype, int lp) {
+    int nb = 0;
+    hipError_t e = hipSuccess;
+    if (lp * (dtype == 0 ? 8 : 4) <= 8) {
+        if (dtype == 0) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_rx_merge<double, 1>, kThreads, 0);
+        else if (lp == 1) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_rx_merge<float, 1>, kThreads, 0);
+        else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_rx_merge<float, 2>, kThreads, 0);
+    } else {
+#define O_RX(T, L) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_rx_merge_wide<T, L>, kThreads, 0)
+        switch (lp) {
+            case 2: if (dtype == 0) O_RX(double, 2); break;
+            case 4: if (dtype == 0) O_RX(double, 4); else O_RX(float, 4); break;
+            case 8: if (dtype == 0) O_RX(double, 8); else O_RX(float, 8); break;
+            case 16: if (dtype == 0) O_RX(double, 16); else O_RX(float, 16); break;
+            case 32: if (dtype == 0) O_RX(double, 32); else O_RX(float, 32); break;
+            default: break;
+        }
+#undef O_RX
+    }
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    return nb;
 }
 
 hipError_t launch_rx(const RxArgs& a, const GateTrig& g, int dtype, int lp, hipStream_t s, int grid) {

@@ -17,11 +17,21 @@ def test_more_than_one_gpu_is_refused():
     assert r.stdout.strip() == ""
 
 
-def test_traffic_figure_is_tied_to_the_kernel_sources():
+def test_traffic_figure_is_tied_to_the_kernel_sources_and_the_workload():
+    """A committed counter figure is used only by a run of the same kernel
+    sources and the same workload key (configuration and step window)."""
+    import argparse
     sys.path.insert(0, ROOT)
     import bench
     sha = bench.kernel_source_sha()
     assert len(sha) == 16 and sha == bench.kernel_source_sha()
-    traffic, src = bench.measured_traffic()
-    if traffic is not None:  # a summary taken on these sources: a plausible per-launch byte count
-        assert src.startswith("k_rx_merge__") and 1e8 < traffic < 1e11
+    args = argparse.Namespace(lanes="none", dtype="f64", eps=1e-4, theta=0.8, theta_zz=-1.5707963267948966,
+                              trunc="magnitude", warmup=18, steps=2)
+    key = bench.workload_key(args)
+    assert key == ("lanes=none dtype=f64 eps=0.0001 theta=0.8 theta_zz=-1.570796 trunc=magnitude "
+                   "steps=19-20")
+    traffic, alg, src = bench.measured_traffic(key)
+    if traffic is not None:  # a summary taken on these sources and this workload
+        assert src.startswith("k_rx_merge__") and 1e8 < traffic < 1e11 and 0.9 < traffic / alg < 3.0
+    other = argparse.Namespace(**{**vars(args), "warmup": 5})
+    assert bench.measured_traffic(bench.workload_key(other)) == (None, None, None)

@@ -234,14 +234,14 @@ def test_fp32_theta_lanes_truncated_expectation_against_oracle():
 def test_fp32_two_sum_127q_eps1e5_against_fp64_per_step():
     """The precision form at its stated threshold: binary32 + two-sum against
     binary64 on the same GPU, 127 q, theta_h = 0.8, eps0 = 1e-5, Trotter steps
-    1..20 while each run stays within a time budget of 150 s (the binary64
+    1..20 while each run stays within a time budget of 55 s (the binary64
     run first, then the binary32 run, one at a time in device memory):
     |delta <Z62>| <= 1e-3 at every step, each step's value printed."""
     import time
     lat = w.eagle_127()
     zz, rx = w.kicked_ising_step(lat, 0.8)
     terms, coef = w.single_pauli_term(lat.n, {62: "Z"})
-    budget, steps = 150.0, 20
+    budget, steps = 55.0, 20
     ez = {}
     for dt in (0, 1):
         g = gpu_sum(lat.n, terms, coef, dtype=dt)

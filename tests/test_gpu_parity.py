@@ -248,3 +248,19 @@ def test_clifford_resort_group_sort_and_radix_fallback():
             assert passes == 1
         else:
             assert passes > 1
+
+
+def test_rx_tiles_finding_their_own_boundaries_equal_oracle():
+    """With the grid's boundary step switched off, every RX tile finds its
+    two boundaries itself (the path a tile takes when they do not arrive in
+    time): the benchmark workload still equals the oracle bit for bit
+    (127 q, theta_h = 0.8, eps0 = 1e-4, 5 steps)."""
+    lat = w.eagle_127()
+    zz, rx = w.kicked_ising_step(lat, 0.8)
+    terms, coef = w.single_pauli_term(lat.n, {62: "Z"})
+    g = gpu_sum(lat.n, terms, coef).set_rx_boundary_prologue(False)
+    o = OracleSum(lat.n, terms, coef)
+    for t in range(5):
+        g.apply_rotation_layer(zz, 1e-4).apply_rotation_layer(rx, 1e-4)
+        o.apply(zz, 1e-4).apply(rx, 1e-4)
+        assert_same_operator(g, o, coeff_exact=True)
