@@ -37,7 +37,9 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
 # (eps0, warmup steps, timed steps, dtype) of the batched forms at one GPU
-LANES_ONE_GPU = {"theta32": (1e-3, 13, 2, "f32"), "obs16": (1e-3, 13, 2, "f32")}
+# (measured: theta32 holds 4.8e7 strings at step 15 at 3e-3; obs16 5.4e8 at 2e-4, while 1e-4
+# outgrows 288 GB at step 6 for both)
+LANES_ONE_GPU = {"theta32": (3e-3, 13, 2, "f32"), "obs16": (2e-4, 13, 2, "f32")}
 
 
 def log(*a):
@@ -154,6 +156,10 @@ def main():
                     help="after the run, repeat it untimed in binary64 (magnitude rule) and report |delta <Z62>| per step")
     ap.add_argument("--trunc", choices=["magnitude", "learned"], default="magnitude",
                     help="learned: the committed trained scorer (127q, Z62, theta 0.8) on top of the magnitude rule")
+    ap.add_argument("--learned-ratio", type=float, default=1.0,
+                    help="learned threshold = ratio x eps (pauli_sum_set_learned)")
+    ap.add_argument("--learned-tol", type=float, default=0.0,
+                    help="fall back to the magnitude rule when the estimated learned error exceeds this (0: never)")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--verbose", action="store_true")
@@ -227,7 +233,7 @@ def main():
         params, _ = S.load_params(os.path.join(ROOT, "paper_2506_13241_amd", "data",
                                                "scorer_eagle127_z62_theta0.8.npz"))
         sc = P.PsScorer(lat.n, *S.feature_table(lat.n, lat.edges, 62)).set_params(params)
-        ps.load_scorer(sc)
+        ps.load_scorer(sc).set_learned(args.learned_ratio, args.learned_tol)
         mode = P.PS_TRUNC_LEARNED
 
     ez_all = []
@@ -301,6 +307,10 @@ def main():
         extra["lanes"] = lanes
         extra["string_lane_updates_per_s"] = updates * lanes / dt
         extra["bytes_per_string_lane"] = bps / lanes
+    if args.trunc == "learned":
+        extra["learned"] = {"ratio": args.learned_ratio, "tol": args.learned_tol,
+                            "passes": int(st["learned_passes"]), "fallbacks": int(st["learned_fallbacks"]),
+                            "last_estimate": st["learned_est"]}
     if st["score_launches"] > 0:
         flop = 2 * (160 * 128 + 128 * 128 + 128) * st["score_in"]
         extra["scorer"] = {
@@ -345,7 +355,8 @@ def main():
             "workload": f"kicked Ising 127q heavy-hex, {what}, "
                         + ("theta_zz=-pi/2, " if abs(args.theta_zz + math.pi / 2) < 1e-15 else f"theta_zz={args.theta_zz}, ")
                         + f"eps0={args.eps} per gate"
-                        + (" + learned truncation once per step" if args.trunc == "learned" else "")
+                        + (f" + learned truncation once per step (ratio {args.learned_ratio:g}, fallback tol "
+                           f"{args.learned_tol:g})" if args.trunc == "learned" else "")
                         + f", Trotter steps {args.warmup + 1}-{args.warmup + args.steps}",
             "qubits": 127,
             "gates_per_step": 271,

@@ -271,6 +271,23 @@ int pauli_sum_lookback_epoch(ps_handle* h, uint32_t* epoch);
  */
 int pauli_sum_set_rx_boundary_prologue(ps_handle* h, int enable);
 
+/*
+ * pauli_sum_set_learned -- the learned rule's threshold and its fallback to
+ * magnitude truncation (Eq. truncation1).  The learned rule of
+ * PS_TRUNC_LEARNED drops a string the magnitude rule keeps when
+ * |O_I,a| * min(1, 10^y) <= eps_ratio * rel_eps * max_I |O_I,a| in every lane
+ * (eps_ratio in (0, 1], default 1).  Before each learned pass the library
+ * estimates the error of those extra drops per lane,
+ * sqrt(sum over them of (|O_I,a| min(1, 10^y))^2) (their contributions to
+ * <Z> with independent signs); with tol > 0, a pass whose estimate exceeds
+ * tol in some lane applies the magnitude rule alone instead.  tol <= 0 (the
+ * default): never fall back.  ps_stats reports the learned passes, how many
+ * fell back, and the last estimate with its sum of |O_I,a| min(1, 10^y)
+ * (lane 0).  Errors: PS_ERR_INVALID (eps_ratio outside (0, 1]),
+ * PS_ERR_NONFINITE (tol).
+ */
+int pauli_sum_set_learned(ps_handle* h, double eps_ratio, double tol);
+
 typedef struct ps_scorer ps_scorer;
 int ps_scorer_create(int n_qubits, const uint64_t* qmask, const uint8_t* letters, const float* scales,
                      void* hip_stream, ps_scorer** out);
@@ -310,6 +327,10 @@ int pauli_sum_load_scorer(ps_handle* h, const ps_scorer* s);
  *                  of the last one (pauli_sum_set_sort_config)
  *   run_merges     general gates sorted by gathering their runs (parents;
  *                  children by class) and merging them pairwise
+ *   learned_passes, learned_fallbacks, learned_est, learned_l1  learned
+ *                  truncation passes, those that fell back to the magnitude
+ *                  rule, and the last pass's error estimate (lane 0; see
+ *                  pauli_sum_set_learned)
  */
 typedef struct {
     double updates, gates;
@@ -321,6 +342,7 @@ typedef struct {
     double score_launches, score_in, score_ms;
     double radix_sorts, sort_digit_bits, sort_items_per_thread;
     double run_merges;
+    double learned_passes, learned_fallbacks, learned_est, learned_l1;
 } ps_stats;
 
 int pauli_sum_set_timing(ps_handle* h, int enable);

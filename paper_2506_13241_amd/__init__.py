@@ -29,6 +29,7 @@ EXPORTED_SYMBOLS = (
     "ps_scorer_forward", "ps_scorer_loss_grad", "ps_scorer_adam_step", "pauli_sum_set_graphs",
     "pauli_sum_histogram", "pauli_sum_set_sort_config", "pauli_sum_histogram_noalloc",
     "pauli_sum_set_lookback_epoch", "pauli_sum_lookback_epoch", "pauli_sum_set_rx_boundary_prologue",
+    "pauli_sum_set_learned",
 )
 N_SCORER_PARAMS = 37249
 SORT_CONFIGS = ((8, 8), (8, 16), (7, 16), (6, 16), (7, 8), (6, 8))  # (digit bits, items per thread)
@@ -49,7 +50,8 @@ class ps_stats(ctypes.Structure):
         "updates", "gates", "rx_launches", "rx_in", "rx_out", "rx_ms", "cliff_launches", "cliff_in", "cliff_ms",
         "sort_passes", "sort_elems", "sort_ms", "bytes_per_string", "graph_replays", "graph_captures",
         "score_launches", "score_in", "score_ms",
-        "radix_sorts", "sort_digit_bits", "sort_items_per_thread", "run_merges")]
+        "radix_sorts", "sort_digit_bits", "sort_items_per_thread", "run_merges",
+        "learned_passes", "learned_fallbacks", "learned_est", "learned_l1")]
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -90,6 +92,7 @@ def load_library(path: str = LIB_PATH):
         "pauli_sum_histogram_noalloc": (I, [P, I, P, I, I, P]),
         "pauli_sum_set_lookback_epoch": (I, [P, ctypes.c_uint32]),
         "pauli_sum_set_rx_boundary_prologue": (I, [P, I]),
+        "pauli_sum_set_learned": (I, [P, D, D]),
         "pauli_sum_lookback_epoch": (I, [P, ctypes.POINTER(ctypes.c_uint32)]),
         "pauli_sum_set_sort_config": (I, [P, I, I]),
         "ps_scorer_create": (I, [I, P, P, P, P, ctypes.POINTER(P)]),
@@ -239,6 +242,11 @@ class PauliSum:
         _check(f(self._h, lane, _ptr(e), e.size - 1, int(signed), _ptr(out)))
         return out
 
+    def set_learned(self, eps_ratio: float = 1.0, tol: float = 0.0):
+        """Learned-rule threshold ratio and fallback tolerance (see include/orqa.h)."""
+        _check(_lib.pauli_sum_set_learned(self._h, float(eps_ratio), float(tol)))
+        return self
+
     def set_rx_boundary_prologue(self, enable: bool = True):
         """enable=False: every RX tile finds its own boundaries (tests of that path)."""
         _check(_lib.pauli_sum_set_rx_boundary_prologue(self._h, int(enable)))
@@ -377,6 +385,10 @@ def pauli_sum_lookback_epoch(ps: PauliSum) -> int:
 
 def pauli_sum_set_rx_boundary_prologue(ps: PauliSum, enable: bool = True):
     return ps.set_rx_boundary_prologue(enable)
+
+
+def pauli_sum_set_learned(ps: PauliSum, eps_ratio: float = 1.0, tol: float = 0.0):
+    return ps.set_learned(eps_ratio, tol)
 
 
 def pauli_sum_load_scorer(ps: PauliSum, scorer: PsScorer):

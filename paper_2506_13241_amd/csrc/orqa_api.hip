@@ -147,7 +147,10 @@ struct ps_handle {
     size_t gates_applied = 0;
     uint64_t n_host = 0;  // size after the last synchronisation
     bool broken = false;
-    // learned truncation
+    // learned truncation: its threshold is learned_ratio * rel_eps; with
+    // learned_tol > 0 a pass whose estimated learned error exceeds it falls
+    // back to the magnitude rule
+    double learned_ratio = 1.0, learned_tol = 0.0;
     bool has_scorer = false;
     ScorerDev scorer{};
     float* gscore = nullptr;  // cap floats
@@ -520,6 +523,8 @@ int enqueue_compact(ps_handle* h, int in, int out, int mx_in, int mx_out, double
         HIP_TRY(launch_scorer_forward(f, h->stream, h->grid / 2));  // two 512-thread workgroups per CU
         rc = ev_end(h, slot);
         if (rc) return rc;
+        HIP_TRY(launch_learned_estimate(h->ctrl, in, h->buf[in].C, h->gscore, h->cap, eps_in, eps_learned, mx_in,
+                                        h->partial, h->dtype, h->LP, h->stream));
     }
     CompactArgs a{};
     a.ctrl = h->ctrl;
@@ -545,6 +550,7 @@ int enqueue_compact(ps_handle* h, int in, int out, int mx_in, int mx_out, double
     a.gate_count = gate_count;
     a.gscore = learned ? h->gscore : nullptr;
     a.eps_learned = learned ? eps_learned : 0.0;
+    a.learned_tol = h->learned_tol;
     size_t slot;
     int rc = ev_begin(h, 1, &slot);
     if (rc) return rc;
@@ -1237,7 +1243,7 @@ int pauli_sum_create(int n_qubits, int n_lanes, int dtype, size_t capacity, cons
     if (hipMalloc(reinterpret_cast<void**>(&h->ctrl), sizeof(Ctrl)) != hipSuccess ||
         hipMalloc(reinterpret_cast<void**>(&h->hist), kSortMaxPasses * 256 * sizeof(uint32_t)) != hipSuccess ||
         hipMalloc(reinterpret_cast<void**>(&h->digit_base), kSortMaxPasses * 256 * sizeof(uint32_t)) != hipSuccess ||
-        hipMalloc(reinterpret_cast<void**>(&h->partial), kReduceBlocks * kMaxLanes * sizeof(double)) != hipSuccess ||
+        hipMalloc(reinterpret_cast<void**>(&h->partial), 2 * kReduceBlocks * kMaxLanes * sizeof(double)) != hipSuccess ||
         hipMalloc(reinterpret_cast<void**>(&h->red_out), kMaxLanes * sizeof(double)) != hipSuccess ||
         hipMalloc(reinterpret_cast<void**>(&h->cgens), kMaxCliffGens * sizeof(CliffGen)) != hipSuccess) {
         (void)hipGetLastError();
@@ -1319,7 +1325,7 @@ int apply_rotation_layer(ps_handle* h, const ps_pauli* gens, const double* theta
     if (trunc_mode == PS_TRUNC_LEARNED && !h->has_scorer)
         return fail(PS_ERR_INVALID, "PS_TRUNC_LEARNED needs pauli_sum_load_scorer first");
     if (std::isnan(rel_eps)) return fail(PS_ERR_NONFINITE, "rel_eps is NaN");
-    const double eps_learned = (trunc_mode == PS_TRUNC_LEARNED && rel_eps > 0.0) ? rel_eps : -1.0;
+    const double eps_learned = (trunc_mode == PS_TRUNC_LEARNED && rel_eps > 0.0) ? rel_eps * h->learned_ratio : -1.0;
     const double eps = (trunc_mode == PS_TRUNC_NONE || !(rel_eps > 0.0)) ? -1.0 : rel_eps;
     for (size_t g = 0; g < n_gates; ++g) {
         if (!validate_key(h->nq, gens[g])) return fail(PS_ERR_INVALID, "generator %zu has bits above n_qubits", g);
@@ -1782,6 +1788,10 @@ int pauli_sum_stats(ps_handle* h, ps_stats* out, int reset) {
     out->score_ms = h->ms[3];
     out->radix_sorts = h->radix_sorts;
     out->run_merges = h->run_merges;
+    out->learned_passes = double(c.learned_passes);
+    out->learned_fallbacks = double(c.learned_fallbacks);
+    out->learned_est = c.learned_est[0];
+    out->learned_l1 = c.learned_l1[0];
     out->sort_digit_bits = kSortCandBits[h->sort_last];
     out->sort_items_per_thread = kSortCandIpt[h->sort_last];
     if (reset) {
@@ -1790,6 +1800,8 @@ int pauli_sum_stats(ps_handle* h, ps_stats* out, int reset) {
         h->ms[3] = 0;
         const uint64_t z2[2] = {0, 0};
         HIP_TRY(hipMemcpyAsync(&h->ctrl->aux[0], z2, sizeof z2, hipMemcpyHostToDevice, h->stream));
+        const uint64_t z2b[2] = {0, 0};
+        HIP_TRY(hipMemcpyAsync(&h->ctrl->learned_passes, z2b, sizeof z2b, hipMemcpyHostToDevice, h->stream));
         c.cnt_updates = c.cnt_rx_in = c.cnt_rx_out = c.cnt_rx_launches = 0;
         c.cnt_cliff_in = c.cnt_cliff_launches = 0;
         HIP_TRY(hipMemcpyAsync(&h->ctrl->cnt_updates, &c.cnt_updates, 6 * sizeof(uint64_t), hipMemcpyHostToDevice,
@@ -1850,6 +1862,16 @@ int pauli_sum_set_sort_config(ps_handle* h, int digit_bits, int items_per_thread
     }
     return fail(PS_ERR_INVALID, "no radix-sort configuration with %d-bit digits and %d items per thread", digit_bits,
                 items_per_thread);
+}
+
+int pauli_sum_set_learned(ps_handle* h, double eps_ratio, double tol) {
+    if (!h) return fail(PS_ERR_INVALID, "handle is NULL");
+    if (!std::isfinite(eps_ratio) || !(eps_ratio > 0.0) || eps_ratio > 1.0)
+        return fail(PS_ERR_INVALID, "eps_ratio must be in (0, 1]");
+    if (!std::isfinite(tol)) return fail(PS_ERR_NONFINITE, "tol is not finite");
+    h->learned_ratio = eps_ratio;
+    h->learned_tol = tol;
+    return PS_OK;
 }
 
 int pauli_sum_set_rx_boundary_prologue(ps_handle* h, int enable) {

@@ -52,6 +52,12 @@ struct Ctrl {
     uint64_t cnt_rx_in, cnt_rx_out, cnt_rx_launches;
     uint64_t cnt_cliff_in, cnt_cliff_launches;
     uint64_t aux[4];
+    // learned truncation: per lane, the estimated error of the strings that
+    // only the learned rule drops, sqrt(sum (|c| min(1, 10^y))^2), and its
+    // sum of |c| min(1, 10^y); passes that fell back to the magnitude rule
+    double learned_est[kMaxLanes];
+    double learned_l1[kMaxLanes];
+    uint64_t learned_passes, learned_fallbacks;
     // tile counters of the look-back kernels, one per workgroup stream
     // (blockIdx modulo kTileStreams), each on a cache line of its own
     alignas(128) uint32_t tile_ctr[kTileStreams][32];
@@ -124,6 +130,7 @@ struct CompactArgs {
     int gate_count;      // gates this pass stands for (measurement counters)
     const float* gscore;  // learned truncation: log10 predicted weight per input string, or null
     double eps_learned;
+    double learned_tol;   // fall back to the magnitude rule when some lane's learned_est exceeds it (<= 0: never)
     // prefix_only: compact only the first ctrl->prefix_len strings of the
     // input (the x == 0 prefix) for a readout, with no other effect on the
     // handle: no maxima, counters or sizes of the operator are touched; the
@@ -304,6 +311,13 @@ hipError_t launch_histogram(const HistArgs& a, int dtype, int lp, hipStream_t s,
 hipError_t launch_reduce(Ctrl* ctrl, int buf, const ulonglong2* X, const void* C, uint64_t cap, int mode,
                          double eps_pend, int mx, double* partial, double* out, int dtype, int lp, hipStream_t s);
 hipError_t launch_fill_u64(uint64_t* p, uint64_t v, size_t n, hipStream_t s);
+// Estimated error of the learned rule on buffer buf (into ctrl->learned_est
+// and learned_l1): strings the magnitude rule keeps (|c| > eps_pend * M in
+// some lane) but the learned rule drops (|c| min(1, 10^y) <= eps_learned * M
+// in every lane).  partial: kReduceBlocks x 2 x lanes doubles.
+hipError_t launch_learned_estimate(Ctrl* ctrl, int buf, const void* C, const float* gscore, uint64_t cap,
+                                   double eps_pend, double eps_learned, int mx, double* partial, int dtype, int lp,
+                                   hipStream_t s);
 // Length of the x == 0 prefix of buffer buf into ctrl->prefix_len.
 hipError_t launch_prefix_len(Ctrl* ctrl, int buf, const ulonglong2* X, hipStream_t s);
 

@@ -766,6 +766,13 @@ __global__ __launch_bounds__(kThreads) void k_compact(CompactArgs A) {
     const uint64_t ntiles = skip ? 0 : (n + kCompactTile - 1) / kCompactTile;
     const uint32_t ep = ctrl->epoch;
     const bool filt = A.eps_in > 0.0;
+    // learned rule, unless its estimated error exceeds the tolerance in some
+    // lane: then this pass applies the magnitude rule alone (the fallback)
+    bool use_learned = A.gscore != nullptr;
+    if (use_learned && A.learned_tol > 0.0) {
+#pragma unroll
+        for (int a = 0; a < LP; ++a) use_learned &= !(ctrl->learned_est[a] > A.learned_tol);
+    }
     if (tid < LP) {
         const double M = bits_to_d(ctrl->maxbits[A.mx_in][tid]);
         sThr[tid] = filt ? A.eps_in * M : -1.0;
@@ -805,7 +812,7 @@ __global__ __launch_bounds__(kThreads) void k_compact(CompactArgs A) {
                 for (int a = 0; a < LP; ++a) cs[k][a] = Cin[p * LP + a];
                 al = true;
                 if (filt) al = keep_row<CT, LP>(cs[k], sThr);
-                if (A.gscore) {  // learned rule: |c| * min(1, 10^y) > eps * M in some lane
+                if (use_learned) {  // learned rule: |c| * min(1, 10^y) > eps * M in some lane
                     const double gw = fmin(1.0, exp10(static_cast<double>(A.gscore[i])));
                     bool keepL = false;
 #pragma unroll
@@ -907,6 +914,10 @@ __global__ __launch_bounds__(kThreads) void k_compact(CompactArgs A) {
             ctrl->cnt_updates += n * uint64_t(A.gate_count);
             ctrl->cnt_cliff_in += n;
             ctrl->cnt_cliff_launches += 1;
+            if (A.gscore) {
+                ctrl->learned_passes += 1;
+                if (!use_learned) ctrl->learned_fallbacks += 1;
+            }
         }
     }
 }
@@ -1101,6 +1112,81 @@ __global__ __launch_bounds__(kThreads) void k_reduce_partial(const Ctrl* __restr
     if (threadIdx.x < LP) {
         const int a = threadIdx.x;
         partial[blockIdx.x * LP + a] = ((sAcc[0][a] + sAcc[1][a]) + sAcc[2][a]) + sAcc[3][a];
+    }
+}
+
+// Learned-rule error estimate (deterministic: fixed chunks, fixed trees).
+// A string the magnitude rule keeps and the learned rule drops adds
+// (|c_a| w)^2 and |c_a| w, w = min(1, 10^y), to lane a.
+template <typename CT, int LP>
+__global__ __launch_bounds__(kThreads) void k_learned_partial(const Ctrl* __restrict__ ctrl, int buf,
+                                                              const CT* __restrict__ C,
+                                                              const float* __restrict__ gscore, uint64_t cap,
+                                                              double eps_pend, double eps_learned, int mx,
+                                                              double* __restrict__ partial) {
+    __shared__ double sAcc[4][2][LP];
+    __shared__ double sThr[LP], sThrL[LP];
+    if (threadIdx.x < LP) {
+        const double M = bits_to_d(ctrl->maxbits[mx][threadIdx.x]);
+        sThr[threadIdx.x] = eps_pend > 0.0 ? eps_pend * M : -1.0;
+        sThrL[threadIdx.x] = eps_learned * M;
+    }
+    __syncthreads();
+    const uint64_t nf = ctrl->nf[buf];
+    const uint64_t len = nf + ctrl->nb[buf];
+    const uint64_t chunk = (len + gridDim.x - 1) / gridDim.x;
+    const uint64_t b0 = blockIdx.x * chunk;
+    const uint64_t b1 = (b0 + chunk < len) ? b0 + chunk : len;
+    double sq[LP], ab[LP];
+#pragma unroll
+    for (int a = 0; a < LP; ++a) sq[a] = ab[a] = 0.0;
+    for (uint64_t i = b0 + threadIdx.x; i < b1; i += kThreads) {
+        const uint64_t p = vphys(i, nf, cap);
+        const double w = fmin(1.0, exp10(static_cast<double>(gscore[i])));
+        bool keepM = false, keepL = false;
+#pragma unroll
+        for (int a = 0; a < LP; ++a) {
+            const double c = absd(C[p * LP + a]);
+            keepM |= c > sThr[a];
+            keepL |= c * w > sThrL[a];
+        }
+        if (!keepM || keepL) continue;
+#pragma unroll
+        for (int a = 0; a < LP; ++a) {
+            const double v = absd(C[p * LP + a]) * w;
+            sq[a] += v * v;
+            ab[a] += v;
+        }
+    }
+    const int wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int a = 0; a < LP; ++a) {
+        double u = sq[a], v = ab[a];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            u += __shfl_xor(u, o, 64);
+            v += __shfl_xor(v, o, 64);
+        }
+        if (lane_id() == 0) {
+            sAcc[wave][0][a] = u;
+            sAcc[wave][1][a] = v;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < 2 * LP) {
+        const int q = threadIdx.x / LP, a = threadIdx.x % LP;
+        partial[(blockIdx.x * 2 + q) * LP + a] = ((sAcc[0][q][a] + sAcc[1][q][a]) + sAcc[2][q][a]) + sAcc[3][q][a];
+    }
+}
+
+template <int LP>
+__global__ void k_learned_final(const double* __restrict__ partial, int nblocks, Ctrl* ctrl) {
+    if (threadIdx.x < 2 * LP) {
+        const int q = threadIdx.x / LP, a = threadIdx.x % LP;
+        double s = 0.0;
+        for (int b = 0; b < nblocks; ++b) s += partial[(b * 2 + q) * LP + a];
+        if (q == 0) ctrl->learned_est[a] = sqrt(s);
+        else ctrl->learned_l1[a] = s;
     }
 }
 
@@ -1327,6 +1413,19 @@ hipError_t launch_reduce(Ctrl* ctrl, int buf, const ulonglong2* X, const void* C
     k_reduce_final<L><<<1, 64, 0, s>>>(partial, kReduceBlocks, out)
     ORQA_DISPATCH(dtype, lp, L_RD);
 #undef L_RD
+    return hipGetLastError();
+}
+
+hipError_t launch_learned_estimate(Ctrl* ctrl, int buf, const void* C, const float* gscore, uint64_t cap,
+                                   double eps_pend, double eps_learned, int mx, double* partial, int dtype, int lp,
+                                   hipStream_t s) {
+#define L_LE(T, L)                                                                                           \
+    k_learned_partial<T, L><<<dim3(kReduceBlocks), dim3(kThreads), 0, s>>>(ctrl, buf, static_cast<const T*>(C), \
+                                                                           gscore, cap, eps_pend, eps_learned, mx, \
+                                                                           partial);                              \
+    k_learned_final<L><<<1, 64, 0, s>>>(partial, kReduceBlocks, ctrl)
+    ORQA_DISPATCH(dtype, lp, L_LE);
+#undef L_LE
     return hipGetLastError();
 }
 
