@@ -316,7 +316,14 @@ constexpr uint32_t kNoTile = 0xFFFFFFFFu;
 template <typename CT, int LP, int KR>
 __device__ __forceinline__ void rx_merge_body(const RxArgs& A, const GateTrig& g) {
     constexpr bool kStageC = LP * sizeof(CT) <= 8;  // coefficients staged in LDS (and held in registers)
+    static_assert(KR == 0 || kStageC, "only rows staged in LDS are held in registers");
     constexpr int KH = KR > 0 ? KR : 1;             // size of the hold arrays
+    // wider rows are read and written in 16-byte chunks, one thread per chunk
+    // (coalesced; a thread always takes the same chunk of a row, so it keeps
+    // the maxima of kVPC lanes only)
+    constexpr int kCPR = kStageC ? 1 : int(LP * sizeof(CT)) / 16;  // chunks per row
+    constexpr int kVPC = kStageC ? LP : LP / kCPR;                  // lanes per chunk
+    static_assert(kStageC || (kCPR >= 1 && 64 % kCPR == 0 && kVPC * kCPR == LP), "row chunks");
     __shared__ ulonglong2 sX[kRxTileMax];
     __shared__ ulonglong2 sZ[kRxTileMax];
     __shared__ CT sC[kStageC ? kRxTileMax * LP : 1];
@@ -342,9 +349,9 @@ __device__ __forceinline__ void rx_merge_body(const RxArgs& A, const GateTrig& g
     const uint32_t ep = ctrl->epoch;
     const bool filt = A.eps_in > 0.0;
     if (tid < LP) sThr[tid] = filt ? A.eps_in * bits_to_d(ctrl->maxbits[A.mx_in][tid]) : -1.0;
-    double vmax[LP];
+    double vmax[kVPC];  // staged rows: every lane; wider rows: the lanes of this thread's chunk
 #pragma unroll
-    for (int a = 0; a < LP; ++a) vmax[a] = 0.0;
+    for (int a = 0; a < kVPC; ++a) vmax[a] = 0.0;
     const int zw = g.zword;
     const uint64_t zmask = 1ull << g.zbit;
     const uint64_t cap = A.cap;
@@ -357,8 +364,6 @@ __device__ __forceinline__ void rx_merge_body(const RxArgs& A, const GateTrig& g
     uint32_t h_tile = kNoTile, h_totA = 0, h_totB = 0;
     uint64_t hxl[KH], hxh[KH], hzl[KH], hzh[KH];  // (scalar words: kept in registers)
     CT hc[KH][kStageC ? LP : 1];
-    uint64_t hp1[kStageC ? 1 : KH], hp2[kStageC ? 1 : KH];
-    uint32_t hk[kStageC ? 1 : KH];
 
     // ---- this gate's tile boundaries, shared out over the grid's waves
     TileDescWords* const desc = reinterpret_cast<TileDescWords*>(A.desc);
@@ -415,9 +420,25 @@ __device__ __forceinline__ void rx_merge_body(const RxArgs& A, const GateTrig& g
                                 keep |= absd(rc[k][a]) > sThr[a];
                             }
                             sAlive[e] = uint8_t(keep);
-                        } else {
-                            sAlive[e] =
-                                filt ? uint8_t(keep_row<CT, LP>(Cin + rx_phys(T, e, nf, cap) * LP, sThr)) : uint8_t(1);
+                        } else if (!filt) {
+                            sAlive[e] = 1;
+                        }
+                    }
+                }
+                if constexpr (!kStageC) {
+                    if (filt) {  // a row is alive when some lane is above its threshold: chunks, then OR
+                        const uint32_t nc = (m * kCPR + kThreads - 1) / kThreads * kThreads;
+                        for (uint32_t c = tid; c < nc; c += kThreads) {
+                            const uint32_t e = c / kCPR, q = c % kCPR;
+                            int keep = 0;
+                            if (e < m) {
+                                const CT* src = Cin + rx_phys(T, e, nf, cap) * LP + q * kVPC;
+#pragma unroll
+                                for (int j = 0; j < kVPC; ++j) keep |= absd(src[j]) > sThr[q * kVPC + j];
+                            }
+#pragma unroll
+                            for (int o = 1; o < kCPR; o <<= 1) keep |= __shfl_xor(keep, o, 64);
+                            if (e < m && q == 0) sAlive[e] = uint8_t(keep);
                         }
                     }
                 }
@@ -590,21 +611,8 @@ __device__ __forceinline__ void rx_merge_body(const RxArgs& A, const GateTrig& g
                 A.Xout[po] = make_ulonglong2(hxl[k], hxh[k]);
                 A.Zout[po] = make_ulonglong2(hzl[k], hzh[k]);
                 CT* dst = Cout + po * LP;
-                if constexpr (kStageC) {
 #pragma unroll
-                    for (int a = 0; a < LP; ++a) dst[a] = hc[k][a];
-                } else {
-                    const uint32_t kind = hk[k] & 3u;
-                    const bool neg = (hk[k] >> 2) == 0u;
-                    const CT* ce = Cin + hp1[k] * LP;
-                    const CT* ce2 = Cin + hp2[k] * LP;
-#pragma unroll
-                    for (int a = 0; a < LP; ++a) {
-                        const CT v = rx_value<CT, LP>(g, a, kind, neg, ce[a], kind == 3 ? ce2[a] : CT(0));
-                        dst[a] = v;
-                        vmax[a] = fmax(vmax[a], absd(v));
-                    }
-                }
+                for (int a = 0; a < (kStageC ? LP : 0); ++a) dst[a] = hc[k][a];
             }
         }
 
@@ -632,10 +640,6 @@ __device__ __forceinline__ void rx_merge_body(const RxArgs& A, const GateTrig& g
                         hc[k][a] = v;
                         vmax[a] = fmax(vmax[a], absd(v));
                     }
-                } else {
-                    hp1[k] = rx_phys(T, e, nf, cap);
-                    hp2[k] = rx_phys(T, e2, nf, cap);
-                    hk[k] = kind | (uint32_t(side) << 2);
                 }
             }
             h_tile = tile;
@@ -676,14 +680,35 @@ __device__ __forceinline__ void rx_merge_body(const RxArgs& A, const GateTrig& g
                     const uint64_t po = side ? cap - 1 - o : o;
                     A.Xout[po] = xo;
                     A.Zout[po] = sZ[e];
-                    CT* dst = Cout + po * LP;
-                    const CT* ce = kStageC ? (sC + e * LP) : (Cin + rx_phys(T, e, nf, cap) * LP);
-                    const CT* ce2 = kStageC ? (sC + e2 * LP) : (Cin + rx_phys(T, e2, nf, cap) * LP);
+                    if constexpr (kStageC) {
+                        CT* dst = Cout + po * LP;
+                        const CT* ce = sC + e * LP;
+                        const CT* ce2 = sC + e2 * LP;
 #pragma unroll
-                    for (int a = 0; a < LP; ++a) {
-                        const CT v = rx_value<CT, LP>(g, a, kind, side == 0, ce[a], kind == 3 ? ce2[a] : CT(0));
-                        dst[a] = v;
-                        vmax[a] = fmax(vmax[a], absd(v));
+                        for (int a = 0; a < LP; ++a) {
+                            const CT v = rx_value<CT, LP>(g, a, kind, side == 0, ce[a], ce2[a]);
+                            dst[a] = v;
+                            vmax[a] = fmax(vmax[a], absd(v));
+                        }
+                    }
+                }
+                if constexpr (!kStageC) {  // coefficients in 16-byte chunks, one thread per chunk
+                    for (uint32_t c = tid; c < tot * kCPR; c += kThreads) {
+                        const uint32_t i = c / kCPR, q = c % kCPR;
+                        const uint32_t en = sOut[side][i];
+                        const uint32_t e = en & 0x3FFu, e2 = (en >> 10) & 0x3FFu, kind = en >> 20;
+                        const uint64_t o = base + i;
+                        if (o >= cap) continue;
+                        const uint64_t po = side ? cap - 1 - o : o;
+                        const CT* ce = Cin + rx_phys(T, e, nf, cap) * LP + q * kVPC;
+                        const CT* ce2 = Cin + rx_phys(T, kind == 3 ? e2 : e, nf, cap) * LP + q * kVPC;
+                        CT* dst = Cout + po * LP + q * kVPC;
+#pragma unroll
+                        for (int j = 0; j < kVPC; ++j) {
+                            const CT v = rx_value<CT, LP>(g, int(q) * kVPC + j, kind, side == 0, ce[j], ce2[j]);
+                            dst[j] = v;
+                            vmax[j] = fmax(vmax[j], absd(v));
+                        }
                     }
                 }
             }
@@ -693,12 +718,16 @@ __device__ __forceinline__ void rx_merge_body(const RxArgs& A, const GateTrig& g
         tile = have ? acquire_tile(ctrl, &sTile) : kNoTile;
     }
 
-    // ---- per-lane max of the outputs
+    // ---- per-lane max of the outputs (wider rows: lane q kVPC + j is held by
+    // the threads whose chunk is q, i.e. lane index q modulo kCPR)
 #pragma unroll
-    for (int a = 0; a < LP; ++a) {
-        const double mx = wave_max_d(vmax[a]);
-        if (lane_id() == 0 && mx > 0.0)
-            atomicMax(reinterpret_cast<unsigned long long*>(&ctrl->maxbits[A.mx_out][a]),
+    for (int j = 0; j < kVPC; ++j) {
+        double mx = vmax[j];
+#pragma unroll
+        for (int o = kCPR; o < 64; o <<= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
+        const int q = lane_id();
+        if (q < kCPR && mx > 0.0)
+            atomicMax(reinterpret_cast<unsigned long long*>(&ctrl->maxbits[A.mx_out][q * kVPC + j]),
                       static_cast<unsigned long long>(d_to_bits(mx)));
     }
     if (finish_launch(ctrl)) {
