@@ -17,17 +17,26 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "orqa_oracle.cpp")
-_LIB = os.path.join(_HERE, "liborqa_oracle.so")
+# ORQA_ORACLE_LIB names another build of the same source (the sanitized one
+# of tests/test_oracle_sanitized.py); by default the in-tree library is used.
+_LIB = os.environ.get("ORQA_ORACLE_LIB") or os.path.join(_HERE, "liborqa_oracle.so")
 
 
-def build(force: bool = True) -> str:
-    """Compile the C++ oracle in place (g++, FP contraction off)."""
-    if force or not os.path.exists(_LIB):
-        tmp = _LIB + ".tmp"
-        subprocess.check_call(["g++", "-O2", "-std=c++17", "-ffp-contract=off", "-fno-fast-math",
-                               "-shared", "-fPIC", "-o", tmp, _SRC])
-        os.replace(tmp, _LIB)
-    return _LIB
+def build(force: bool = True, out: str | None = None, sanitize: bool = False) -> str:
+    """Compile the C++ oracle (g++, FP contraction off) to `out` (default: the
+    library this module loads).  sanitize=True adds AddressSanitizer and
+    UndefinedBehaviorSanitizer, every report fatal; such a build is loaded
+    only by a process that has the ASan runtime preloaded."""
+    out = out or _LIB
+    if force or not os.path.exists(out):
+        tmp = out + ".tmp"
+        cmd = ["g++", "-O2", "-std=c++17", "-ffp-contract=off", "-fno-fast-math", "-shared", "-fPIC"]
+        if sanitize:
+            cmd += ["-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+                    "-fno-sanitize-recover=all"]
+        subprocess.check_call(cmd + ["-o", tmp, _SRC])
+        os.replace(tmp, out)
+    return out
 
 
 _lib = None
