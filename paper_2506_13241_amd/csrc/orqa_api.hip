@@ -502,8 +502,51 @@ int lb_reserve(ps_handle* h, uint64_t k) {
 
 // ---------------------------------------------------------------- stages
 
+// A Clifford run's generators for the pass: weight-2 generators grouped by
+// qubit offset (one slot per lower qubit and offset; a repeated pair, or more
+// offsets than kMaxCliffGroups, stays in the one-by-one list with every other
+// generator).  The generators commute, so the grouping does not change the
+// product.
+void group_cliff_gens(const std::vector<CliffGen>& gens, std::vector<CliffGroup>& groups,
+                      std::vector<CliffGen>& rest) {
+    groups.clear();
+    rest.clear();
+    for (const CliffGen& g : gens) {
+        const int w = __builtin_popcountll(g.z0) + __builtin_popcountll(g.z1);
+        bool placed = false;
+        if (w == 2) {
+            const int a = g.z0 ? __builtin_ctzll(g.z0) : 64 + __builtin_ctzll(g.z1);
+            const uint64_t hi0 = g.z0 & ~(a < 64 ? (1ull << a) : 0ull);
+            const uint64_t hi1 = g.z1 & ~(a >= 64 ? (1ull << (a - 64)) : 0ull);
+            const int b = hi0 ? __builtin_ctzll(hi0) : 64 + __builtin_ctzll(hi1);
+            const uint32_t d = uint32_t(b - a);
+            CliffGroup* grp = nullptr;
+            for (CliffGroup& c : groups)
+                if (c.d == d) grp = &c;
+            if (!grp && groups.size() < size_t(kMaxCliffGroups)) {
+                groups.push_back(CliffGroup{0, 0, 0, 0, d, 0});
+                grp = &groups.back();
+            }
+            const uint64_t m0 = a < 64 ? (1ull << a) : 0ull, m1 = a >= 64 ? (1ull << (a - 64)) : 0ull;
+            if (grp && !((grp->k0 | grp->n0) & m0) && !((grp->k1 | grp->n1) & m1)) {
+                if (g.kodd) {
+                    grp->k0 |= m0;
+                    grp->k1 |= m1;
+                }
+                if (g.neg) {
+                    grp->n0 |= m0;
+                    grp->n1 |= m1;
+                }
+                placed = true;
+            }
+        }
+        if (!placed) rest.push_back(g);
+    }
+}
+
 int enqueue_compact(ps_handle* h, int in, int out, int mx_in, int mx_out, double eps_in, const CliffGen* gens,
-                    int ngens, bool with_rank, int gate_count = 0, double eps_learned = -1.0) {
+                    int ngens, bool with_rank, int gate_count = 0, double eps_learned = -1.0,
+                    const CliffGroup* groups = nullptr, int ngroups = 0) {
     const bool learned = eps_learned > 0.0;
     if (learned) {  // score every input string, then the compaction applies the learned rule
         ScorerFwdArgs f{};
@@ -547,6 +590,8 @@ int enqueue_compact(ps_handle* h, int in, int out, int mx_in, int mx_out, double
     a.xrot = h->xrot;
     a.gens = gens;
     a.ngens = ngens;
+    a.groups = groups;
+    a.ngroups = ngroups;
     a.gate_count = gate_count;
     a.gscore = learned ? h->gscore : nullptr;
     a.eps_learned = learned ? eps_learned : 0.0;
@@ -917,7 +962,7 @@ int pick_sort_candidate(const ps_handle* h, int kind, int cls, uint64_t n) {
 }
 
 int sort_by_rank_z(ps_handle* h, int b, int* result, bool full_key = false, bool try_groups = true,
-                   bool* overflowed = nullptr, int run_bits = -1) {
+                   bool* overflowed = nullptr, int run_bits = -1, bool xor_groups = false) {
     if (overflowed) *overflowed = false;
     Ctrl c;
     int rc = read_ctrl(h, &c);
@@ -941,10 +986,11 @@ int sort_by_rank_z(ps_handle* h, int b, int* result, bool full_key = false, bool
             g.Ls = h->lo[b];
             g.Ld = h->lo[1 - b];
         }
+        g.xor_order = xor_groups ? 1 : 0;
         size_t slot;
         rc = ev_begin(h, 2, &slot);
         if (rc) return rc;
-        HIP_TRY(launch_group_sort(g, h->dtype, h->LP, h->stream, h->grid / 2));
+        HIP_TRY(launch_group_sort(g, h->dtype, h->LP, h->stream, xor_groups ? h->grid : h->grid / 2));
         rc = ev_end(h, slot);
         if (rc) return rc;
         Ctrl c2;
@@ -1245,7 +1291,8 @@ int pauli_sum_create(int n_qubits, int n_lanes, int dtype, size_t capacity, cons
         hipMalloc(reinterpret_cast<void**>(&h->digit_base), kSortMaxPasses * 256 * sizeof(uint32_t)) != hipSuccess ||
         hipMalloc(reinterpret_cast<void**>(&h->partial), 2 * kReduceBlocks * kMaxLanes * sizeof(double)) != hipSuccess ||
         hipMalloc(reinterpret_cast<void**>(&h->red_out), kMaxLanes * sizeof(double)) != hipSuccess ||
-        hipMalloc(reinterpret_cast<void**>(&h->cgens), kMaxCliffGens * sizeof(CliffGen)) != hipSuccess) {
+        hipMalloc(reinterpret_cast<void**>(&h->cgens),
+                  kMaxCliffGens * sizeof(CliffGen) + kMaxCliffGroups * sizeof(CliffGroup)) != hipSuccess) {
         (void)hipGetLastError();
         return bail(fail(PS_ERR_CAPACITY, "hipMalloc failed for handle scratch"));
     }
@@ -1510,11 +1557,18 @@ int apply_rotation_layer(ps_handle* h, const ps_pauli* gens, const double* theta
                 if (rc) return rc;
                 h->xrot = (h->xrot + 1) % h->nq;
             } else {
-                if (!s.gens.empty())
-                    HIP_TRY(hipMemcpyAsync(h->cgens, s.gens.data(), s.gens.size() * sizeof(CliffGen),
+                std::vector<CliffGroup> groups;
+                std::vector<CliffGen> rest;
+                group_cliff_gens(s.gens, groups, rest);
+                CliffGroup* dgroups = reinterpret_cast<CliffGroup*>(h->cgens + kMaxCliffGens);
+                if (!rest.empty())
+                    HIP_TRY(hipMemcpyAsync(h->cgens, rest.data(), rest.size() * sizeof(CliffGen),
                                            hipMemcpyHostToDevice, h->stream));
-                rc = enqueue_compact(h, in, out, mx_in, mx_out, h->pend, h->cgens, int(s.gens.size()),
-                                     s.needs_sort, int(s.gate_count), eps_learned);
+                if (!groups.empty())
+                    HIP_TRY(hipMemcpyAsync(dgroups, groups.data(), groups.size() * sizeof(CliffGroup),
+                                           hipMemcpyHostToDevice, h->stream));
+                rc = enqueue_compact(h, in, out, mx_in, mx_out, h->pend, h->cgens, int(rest.size()),
+                                     s.needs_sort, int(s.gate_count), eps_learned, dgroups, int(groups.size()));
                 if (rc) return rc;
                 if (!s.gens.empty()) HIP_TRY(hipStreamSynchronize(h->stream));  // cgens reused by the next run
             }
@@ -1559,7 +1613,8 @@ int apply_rotation_layer(ps_handle* h, const ps_pauli* gens, const double* theta
         h->n_host = c.nf[h->cur] + c.nb[h->cur];
         if (sort_after) {
             int res = h->cur;
-            rc = sort_by_rank_z(h, h->cur, &res);
+            // after a Clifford run: each x-group is its sorted run XORed with one mask
+            rc = sort_by_rank_z(h, h->cur, &res, false, true, nullptr, -1, true);
             if (rc) return rc;
             h->cur = res;
             rc = check_no_error(h, "re-sort");

@@ -76,6 +76,7 @@ __device__ __forceinline__ double wave_max_d(double v) {
 }
 
 // Exclusive scan over the 256 threads of a block.  s_wave: 4 words of LDS.
+template <int NW = kThreads / 64>
 __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* s_wave, uint32_t& total) {
     const int w = threadIdx.x >> 6;
     const uint32_t inc = wave_incl_scan(v);
@@ -83,7 +84,7 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* s_wave
     __syncthreads();
     uint32_t off = 0, tot = 0;
 #pragma unroll
-    for (int i = 0; i < kThreads / 64; ++i) {
+    for (int i = 0; i < NW; ++i) {
         const uint32_t s = s_wave[i];
         off += (i < w) ? s : 0u;
         tot += s;

@@ -9,6 +9,7 @@ namespace orqa {
 
 constexpr int kMaxLanes = 32;
 constexpr int kMaxCliffGens = 512;  // Clifford generators fused into one pass
+constexpr int kMaxCliffGroups = 32; // offset groups of weight-2 generators (CliffGroup)
 
 // Error bits raised by kernels in Ctrl::err.
 constexpr uint32_t kErrCapacity = 1u;
@@ -86,6 +87,18 @@ struct CliffGen {
     uint32_t neg;  // kodd: sin(theta) = -1; else: cos(theta) = -1
 };
 
+// Weight-2 Z-only generators Z_a Z_(a+d) of one Clifford run that share the
+// qubit offset d, as masks over the lower qubit a: k for those with
+// sin(theta) = +-1 (the string is multiplied by Z_a Z_(a+d)), n for those
+// whose factor is negative.  A run's generators all commute, so the pass
+// applies them in any grouping.
+struct CliffGroup {
+    uint64_t k0, k1;
+    uint64_t n0, n1;
+    uint32_t d;
+    uint32_t pad;
+};
+
 struct Buf {
     ulonglong2* X;  // stored (rotated) x mask
     ulonglong2* Z;
@@ -125,8 +138,10 @@ struct CompactArgs {
     uint64_t max_tiles;
     double eps_in;
     int nq, xrot;
-    const CliffGen* gens;
+    const CliffGen* gens;   // generators applied one by one
     int ngens;
+    const CliffGroup* groups;  // weight-2 generators by qubit offset
+    int ngroups;
     int gate_count;      // gates this pass stands for (measurement counters)
     const float* gscore;  // learned truncation: log10 predicted weight per input string, or null
     double eps_learned;
@@ -196,6 +211,7 @@ struct GroupSortArgs {
     void* Cd;
     const float* Ls;  // low words moved with the strings (binary32 general gates), or NULL
     float* Ld;
+    int xor_order;    // every group is a z-sorted run XORed with one mask (after a Clifford run)
 };
 hipError_t launch_group_sort(const GroupSortArgs& a, int dtype, int lp, hipStream_t s, int grid);
 

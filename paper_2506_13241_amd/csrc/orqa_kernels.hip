@@ -761,24 +761,35 @@ __global__ __launch_bounds__(kThreads) void k_rx_merge_wide(RxArgs A, GateTrig g
 }
 
 // ================================================================ Clifford pass / compaction
-// Reads the virtual input array, applies the pending truncation, then (if
-// ngens > 0) every Z-only Clifford generator in order (each a signed
-// permutation of strings: x unchanged, z ^= z_J, coefficient times
-// sign(B(K,J)) * sin(theta) when the string anticommutes), and writes the
+// Reads the virtual input array, applies the pending truncation, then (if the
+// run has generators) a run of Z-only Clifford rotations, and writes the
 // survivors compacted to the front of the output.  rank_out (optional)
 // receives the index of each string's x-group, the major key of the re-sort.
+//
+// One Z-only generator J at a Clifford angle maps an anticommuting string
+// sigma_I (Eq. update_rule with cos = 0 or sin = 0) to sin(theta) i sigma_J
+// sigma_I = sin(theta) (-1)^[e = 1 mod 4] sigma_K, K = (x, z ^ z_J), with
+// e = |x & z_K| - |x & z_I|, or to cos(theta) sigma_I.  The generators of a
+// run commute, so their product is applied at once: z_f = z ^ (XOR of z_J
+// over the anticommuting generators with sin = +-1), and the product of the
+// factors (-1)^[e_k = 1 mod 4] = i^(e_k + 1) telescopes to
+// i^(|x & z_f| - |x & z| + K), K the number of those generators; the
+// negative sin or cos of each anticommuting generator adds its own sign.
 
-__device__ __forceinline__ bool child_sign_negative_z(const ulonglong2& x, const ulonglong2& zI,
-                                                      const ulonglong2& zK) {
-    // sigma_K sigma_J = i^e sigma_I with x_J = 0:
-    // e = |x & z_K| - |x & z_I| (mod 4); the child factor is +1 for e = 3, -1 for e = 1.
-    const int e = k_popc_and(x, zK) - k_popc_and(x, zI);
-    return (e & 3) == 1;
+__device__ __forceinline__ ulonglong2 shr128(const ulonglong2& v, uint32_t d) {  // 0 < d < 128
+    if (d >= 64u) return make_ulonglong2(v.y >> (d - 64u), 0ull);
+    return make_ulonglong2((v.x >> d) | (v.y << (64u - d)), v.y >> d);
+}
+
+__device__ __forceinline__ ulonglong2 shl128(const ulonglong2& v, uint32_t d) {  // 0 < d < 128
+    if (d >= 64u) return make_ulonglong2(0ull, v.x << (d - 64u));
+    return make_ulonglong2(v.x << d, (v.y << d) | (v.x >> (64u - d)));
 }
 
 template <typename CT, int LP>
 __global__ __launch_bounds__(kThreads) void k_compact(CompactArgs A) {
     __shared__ CliffGen sG[kMaxCliffGens];
+    __shared__ CliffGroup sGrp[kMaxCliffGroups];
     __shared__ uint32_t sWave[4];
     __shared__ uint32_t sTile;
     __shared__ uint64_t sBase[2];
@@ -808,6 +819,8 @@ __global__ __launch_bounds__(kThreads) void k_compact(CompactArgs A) {
         sThrL[tid] = A.eps_learned * M;
     }
     for (int i = tid; i < A.ngens; i += kThreads) sG[i] = A.gens[i];
+    for (int i = tid; i < A.ngroups; i += kThreads) sGrp[i] = A.groups[i];
+    const bool cliff = A.ngens > 0 || A.ngroups > 0;
     double vmax[LP];
 #pragma unroll
     for (int a = 0; a < LP; ++a) vmax[a] = 0.0;
@@ -889,20 +902,33 @@ __global__ __launch_bounds__(kThreads) void k_compact(CompactArgs A) {
             if (!((balA[k] >> lane) & 1ull)) continue;
             ulonglong2 z = zs[k];
             bool neg = false;
-            if (A.ngens > 0) {
+            if (cliff) {
                 const ulonglong2 x = rotl_n(xs[k], A.xrot, A.nq);
+                int K = 0, nneg = 0;
+                for (int gi = 0; gi < A.ngroups; ++gi) {
+                    // bit a of c: x_a != x_(a+d), i.e. Z_a Z_(a+d) anticommutes
+                    const uint32_t d = __builtin_amdgcn_readfirstlane(sGrp[gi].d);
+                    const ulonglong2 y = shr128(x, d);
+                    const uint64_t c0 = x.x ^ y.x, c1 = x.y ^ y.y;
+                    const ulonglong2 ck = make_ulonglong2(c0 & sGrp[gi].k0, c1 & sGrp[gi].k1);
+                    const ulonglong2 up = shl128(ck, d);
+                    z.x ^= ck.x ^ up.x;
+                    z.y ^= ck.y ^ up.y;
+                    K += __popcll(ck.x) + __popcll(ck.y);
+                    nneg += __popcll(c0 & sGrp[gi].n0) + __popcll(c1 & sGrp[gi].n1);
+                }
                 for (int gi = 0; gi < A.ngens; ++gi) {
                     const CliffGen G = sG[gi];
-                    const int par = (__popcll(x.x & G.z0) + __popcll(x.y & G.z1)) & 1;
-                    if (!par) continue;
+                    if (!((__popcll(x.x & G.z0) + __popcll(x.y & G.z1)) & 1)) continue;
                     if (G.kodd) {
-                        const ulonglong2 zk = make_ulonglong2(z.x ^ G.z0, z.y ^ G.z1);
-                        neg ^= child_sign_negative_z(x, z, zk) ^ (G.neg != 0u);
-                        z = zk;
-                    } else {
-                        neg ^= (G.neg != 0u);
+                        z.x ^= G.z0;
+                        z.y ^= G.z1;
+                        ++K;
                     }
+                    nneg += int(G.neg);
                 }
+                const int e = k_popc_and(x, z) - k_popc_and(x, zs[k]) + K;  // even
+                neg = ((e & 3) == 2) != ((nneg & 1) != 0);
             }
             A.Xout[o] = xs[k];
             A.Zout[o] = z;
@@ -1294,13 +1320,60 @@ hipError_t launch_sort_hist(Ctrl* ctrl, int buf, const uint32_t* R, const ulongl
 // z order inside each group is lost (every z of a group was XORed with the
 // same mask).  The same holds after a general rotation with x_J = 0, whose
 // children stay in their parent's group.  When no group exceeds kGsMaxGroup
-// strings, each group is sorted by z inside one workgroup: a string's new
-// position is its group's start plus the number of group members with a
-// smaller z, equal z counting for the members before it (a stable order, so
-// the duplicate keys a rotation creates land next to each other).  Groups keep their positions, so no prefix sum across
-// workgroups is needed.  Workgroup tiles cover kGsTile positions and own the
-// groups that start there.  A group that would not fit sets ctrl->aux[2] and
-// the caller falls back to the radix sort (the input is left untouched).
+// strings, each group is sorted by z inside one workgroup, in place of the
+// group's positions, so no prefix sum across workgroups is needed.  Workgroup
+// tiles cover kGsTile positions and own the groups that start there.  A group
+// that would not fit sets ctrl->aux[2] and the caller falls back to the radix
+// sort (the input is left untouched).
+
+// The groups a tile owns: [a, b) from the first group start at or after t0 to
+// the first at or after t1 (or n), found one chunk of kGsThreads positions at
+// a time.  Returns 0 when no group starts in the tile, -1 when a group is
+// longer than kGsMaxGroup (ctrl->aux[2] is set), 1 otherwise.  Called by the
+// whole workgroup.
+__device__ int gs_tile_groups(const GroupSortArgs& A, uint64_t n, uint64_t t0, uint64_t t1, uint32_t& sA,
+                              uint32_t& sB, uint64_t& a, uint64_t& b) {
+    const int tid = threadIdx.x;
+    if (tid == 0) {
+        sA = 0xFFFFFFFFu;
+        sB = 0xFFFFFFFFu;
+    }
+    __syncthreads();
+    for (int c = 0; c < kGsMaxGroup; c += kGsThreads) {
+        const int i = c + tid;
+        const uint64_t p = t0 + i, q = t1 + i;
+        if (i < kGsMaxGroup) {
+            if (p < n && (p == 0 || !k_eq(A.Xs[p], A.Xs[p - 1]))) atomicMin(&sA, uint32_t(i));
+            if (q < n && !k_eq(A.Xs[q], A.Xs[q - 1])) atomicMin(&sB, uint32_t(i));
+        }
+        __syncthreads();
+        const uint64_t next = uint64_t(c) + kGsThreads;
+        const bool doneA = sA != 0xFFFFFFFFu || t0 + next >= n;
+        const bool doneB = t1 >= n || sB != 0xFFFFFFFFu || t1 + next >= n;
+        __syncthreads();  // every thread has read sA and sB before the next chunk updates them
+        if (doneA && doneB) break;
+    }
+    // A search window of full length without a group start means a group
+    // longer than kGsMaxGroup; one cut short by the end of the operator only
+    // means that no group starts there.
+    const bool full_a = t0 + kGsMaxGroup <= n, full_b = t1 + kGsMaxGroup <= n;
+    const bool over = (sA == 0xFFFFFFFFu && full_a) || (t1 < n && sB == 0xFFFFFFFFu && full_b);
+    if (over) {
+        if (tid == 0) atomicOr(reinterpret_cast<unsigned int*>(&A.ctrl->aux[2]), 1u);
+        __syncthreads();
+        return -1;
+    }
+    a = sA == 0xFFFFFFFFu ? n : t0 + sA;
+    b = (t1 < n && sB != 0xFFFFFFFFu) ? t1 + sB : n;
+    const int own = a < t1 ? 1 : 0;  // else the tile's strings belong to an earlier tile's group
+    __syncthreads();                 // sA, sB read by every thread before the next tile resets them
+    return own;
+}
+
+// Any group order: a string's new position is its group's start plus the
+// number of group members with a smaller z, equal z counting for the members
+// before it (a stable order, so the duplicate keys a rotation creates land
+// next to each other).
 template <typename CT, int LP>
 __global__ __launch_bounds__(kGsThreads) void k_group_sort(GroupSortArgs A) {
     __shared__ ulonglong2 sZ[kGsCap];
@@ -1319,43 +1392,8 @@ __global__ __launch_bounds__(kGsThreads) void k_group_sort(GroupSortArgs A) {
     for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         const uint64_t t0 = tile * kGsTile;
         const uint64_t t1 = t0 + kGsTile < n ? t0 + kGsTile : n;
-        if (tid == 0) {
-            sA = 0xFFFFFFFFu;
-            sB = 0xFFFFFFFFu;
-        }
-        __syncthreads();
-        // first group start at or after t0 (a) and at or after t1 (b), one
-        // chunk of kGsThreads positions at a time until both are found
-        for (int c = 0; c < kGsMaxGroup; c += kGsThreads) {
-            const int i = c + tid;
-            const uint64_t p = t0 + i, q = t1 + i;
-            if (i < kGsMaxGroup) {
-                if (p < n && (p == 0 || !k_eq(A.Xs[p], A.Xs[p - 1]))) atomicMin(&sA, uint32_t(i));
-                if (q < n && !k_eq(A.Xs[q], A.Xs[q - 1])) atomicMin(&sB, uint32_t(i));
-            }
-            __syncthreads();
-            const uint64_t next = uint64_t(c) + kGsThreads;
-            const bool doneA = sA != 0xFFFFFFFFu || t0 + next >= n;
-            const bool doneB = t1 >= n || sB != 0xFFFFFFFFu || t1 + next >= n;
-            __syncthreads();  // every thread has read sA and sB before the next chunk updates them
-            if (doneA && doneB) break;
-        }
-        // A search window of full length without a group start means a group
-        // longer than kGsMaxGroup; one cut short by the end of the operator
-        // only means that no group starts there.
-        const bool full_a = t0 + kGsMaxGroup <= n, full_b = t1 + kGsMaxGroup <= n;
-        const bool over = (sA == 0xFFFFFFFFu && full_a) || (t1 < n && sB == 0xFFFFFFFFu && full_b);
-        if (over) {
-            if (tid == 0) atomicOr(reinterpret_cast<unsigned int*>(&ctrl->aux[2]), 1u);
-            __syncthreads();
-            continue;
-        }
-        const uint64_t a = sA == 0xFFFFFFFFu ? n : t0 + sA;
-        const uint64_t b = (t1 < n && sB != 0xFFFFFFFFu) ? t1 + sB : n;
-        if (a >= t1) {  // no group starts here: the tile's strings belong to an earlier tile's group
-            __syncthreads();
-            continue;
-        }
+        uint64_t a, b;
+        if (gs_tile_groups(A, n, t0, t1, sA, sB, a, b) <= 0) continue;
         const uint32_t m = uint32_t(b - a);  // <= kGsCap by construction
         // stage z and the group-start flags; keep x and coefficients in registers
         constexpr bool kRegC = LP * sizeof(CT) <= 16;  // wider rows are copied at write time
@@ -1410,7 +1448,163 @@ __global__ __launch_bounds__(kGsThreads) void k_group_sort(GroupSortArgs A) {
     }
 }
 
+// Groups that are z-sorted runs XORed with one mask each (the output of a
+// Clifford run, whose input is sorted by (x, z) and whose generators add the
+// same z mask to every string of an x-group).  The new order of a group is
+// the binary trie of its old keys with the two children of some nodes
+// swapped.  The adjacent pair (e-1, e), whose highest differing bit is D_e,
+// splits the node [PG, NG) at e, PG the nearest position before e and NG the
+// nearest after it whose pair differs in a higher bit (a group start counts as
+// higher than any bit); the two halves swap when z_(e-1) > z_e after the XOR,
+// which moves [PG, e) right by NG - e and [e, NG) left by e - PG.  The moves
+// of all nodes meet in a difference array whose prefix sum is each string's
+// displacement inside its group: O(depth of the trie) work per string in
+// place of a scan of its whole group.
+__device__ __forceinline__ uint32_t hdb128(const ulonglong2& t) {  // t != 0
+    return t.y ? 127u - uint32_t(__clzll(t.y)) : 63u - uint32_t(__clzll(t.x));
+}
+
+template <typename CT, int LP>
+__global__ __launch_bounds__(kGsThreads, 4) void k_group_sort_xor(GroupSortArgs A) {
+    constexpr int kPad = kGsCap + 64;
+    constexpr uint8_t kTop = 0xFF;                   // group start, and every entry from m on
+    __shared__ __align__(16) uint8_t sD[kPad];        // D_e
+    __shared__ uint8_t sBM[kPad / 32];               // maxima of sD over 32-entry blocks
+    __shared__ uint32_t sDiff[kGsCap + 1];           // displacements (two's complement)
+    __shared__ uint32_t sWave[kGsThreads / 64];
+    __shared__ uint32_t sA, sB;
+    Ctrl* ctrl = A.ctrl;
+    const CT* __restrict__ Cs = static_cast<const CT*>(A.Cs);
+    CT* __restrict__ Cd = static_cast<CT*>(A.Cd);
+    const int tid = threadIdx.x;
+    const uint64_t n = ctrl->nf[A.in_buf];
+    const uint64_t ntiles = ctrl->err ? 0 : (n + kGsTile - 1) / kGsTile;
+    if (blockIdx.x == 0 && tid == 0 && ctrl->err == 0u) {
+        ctrl->nf[A.out_buf] = n;
+        ctrl->nb[A.out_buf] = 0;
+    }
+    for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const uint64_t t0 = tile * kGsTile;
+        const uint64_t t1 = t0 + kGsTile < n ? t0 + kGsTile : n;
+        uint64_t a, b;
+        if (gs_tile_groups(A, n, t0, t1, sA, sB, a, b) <= 0) continue;
+        const uint32_t m = uint32_t(b - a);  // <= kGsCap by construction
+        // the coefficients stay in registers until the write; x and z are read
+        // again there (the tile's strings are still in the cache)
+        constexpr bool kRegC = LP * sizeof(CT) <= 16;
+        CT cr[kGsIPT][kRegC ? LP : 1];
+        uint32_t swap = 0;  // bit k: the pair ending at element k swaps its node
+#pragma unroll
+        for (int k = 0; k < kGsIPT; ++k) {
+            const uint32_t e = k * kGsThreads + tid;
+            const uint64_t p = a + (e < m ? e : 0u);
+            if constexpr (kRegC) {
+#pragma unroll
+                for (int l = 0; l < LP; ++l) cr[k][l] = Cs[p * LP + l];
+            }
+            if (e < m) {
+                uint8_t d = kTop;
+                if (e != 0 && k_eq(A.Xs[p], A.Xs[p - 1])) {
+                    const ulonglong2 z = A.Zs[p], zp = A.Zs[p - 1];
+                    d = uint8_t(hdb128(make_ulonglong2(zp.x ^ z.x, zp.y ^ z.y)));
+                    swap |= uint32_t(k_lt(z, zp)) << k;
+                }
+                sD[e] = d;
+            }
+        }
+        const uint32_t mend = (m & ~31u) + 64u;  // blocks read by the searches end here
+        for (uint32_t i = m + tid; i < mend; i += kGsThreads) sD[i] = kTop;
+        for (uint32_t i = tid; i <= m; i += kGsThreads) sDiff[i] = 0u;
+        __syncthreads();
+        for (uint32_t j = tid; j < mend / 32; j += kGsThreads) {
+            const uint32_t* w = reinterpret_cast<const uint32_t*>(sD + 32 * j);
+            uint32_t mx = 0;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const uint32_t v = w[q];
+                mx = max(mx, max(max(v & 0xFFu, (v >> 8) & 0xFFu), max((v >> 16) & 0xFFu, v >> 24)));
+            }
+            sBM[j] = uint8_t(mx);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < kGsIPT; ++k) {
+            if (!((swap >> k) & 1u)) continue;
+            const int e = k * kGsThreads + tid;
+            const uint8_t d = sD[e];
+            // PG: sD[gs] = kTop > d bounds the walk to the left
+            int pg = e - 1;
+            const int lo = pg & ~31;
+            while (pg >= lo && sD[pg] <= d) --pg;
+            if (pg < lo) {
+                int blk = (lo >> 5) - 1;
+                while (sBM[blk] <= d) --blk;
+                pg = blk * 32 + 31;
+                while (sD[pg] <= d) --pg;
+            }
+            // NG: sD[m] = kTop bounds the walk to the right
+            int ng = e + 1;
+            const int hi = ng | 31;
+            while (ng <= hi && sD[ng] <= d) ++ng;
+            if (ng > hi) {
+                int blk = (hi >> 5) + 1;
+                while (sBM[blk] <= d) ++blk;
+                ng = blk * 32;
+                while (sD[ng] <= d) ++ng;
+            }
+            const uint32_t R = uint32_t(ng - e), L = uint32_t(e - pg);
+            atomicAdd(&sDiff[pg], R);
+            atomicAdd(&sDiff[e], 0u - (R + L));
+            atomicAdd(&sDiff[ng], L);
+        }
+        __syncthreads();
+        // inclusive prefix sum of sDiff[0, m): kGsIPT consecutive entries per thread
+        {
+            const uint32_t base = uint32_t(tid) * kGsIPT;
+            uint32_t loc[kGsIPT], run = 0;
+#pragma unroll
+            for (int q = 0; q < kGsIPT; ++q) {
+                run += (base + q < m) ? sDiff[base + q] : 0u;
+                loc[q] = run;
+            }
+            uint32_t tot;
+            const uint32_t off = block_excl_scan<kGsThreads / 64>(run, sWave, tot);
+#pragma unroll
+            for (int q = 0; q < kGsIPT; ++q)
+                if (base + q < m) sDiff[base + q] = loc[q] + off;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < kGsIPT; ++k) {
+            const uint32_t e = k * kGsThreads + tid;
+            if (e >= m) continue;
+            const uint64_t d = a + e + uint64_t(int64_t(int32_t(sDiff[e])));
+            A.Xd[d] = A.Xs[a + e];
+            A.Zd[d] = A.Zs[a + e];
+            if (A.Ls) {
+#pragma unroll
+                for (int l = 0; l < LP; ++l) A.Ld[d * LP + l] = A.Ls[(a + e) * LP + l];
+            }
+            if constexpr (kRegC) {
+#pragma unroll
+                for (int l = 0; l < LP; ++l) Cd[d * LP + l] = cr[k][l];
+            } else {
+                const uint64_t p = a + e;
+#pragma unroll 4
+                for (int l = 0; l < LP; ++l) Cd[d * LP + l] = Cs[p * LP + l];
+            }
+        }
+        __syncthreads();
+    }
+}
+
 hipError_t launch_group_sort(const GroupSortArgs& a, int dtype, int lp, hipStream_t s, int grid) {
+    if (a.xor_order) {
+#define L_GSX(T, L) k_group_sort_xor<T, L><<<dim3(grid), dim3(kGsThreads), 0, s>>>(a)
+        ORQA_DISPATCH(dtype, lp, L_GSX);
+#undef L_GSX
+        return hipGetLastError();
+    }
 #define L_GS(T, L) k_group_sort<T, L><<<dim3(grid), dim3(kGsThreads), 0, s>>>(a)
     ORQA_DISPATCH(dtype, lp, L_GS);
 #undef L_GS

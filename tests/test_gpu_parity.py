@@ -91,6 +91,36 @@ def test_clifford_zz_layer_and_resort():
     assert_same_operator(g, o, coeff_exact=True)
 
 
+def test_clifford_run_of_mixed_z_generators():
+    """A run of Z-only Clifford rotations through every branch of the pass's
+    composite form: weight-2 generators at 40 distinct qubit offsets (more
+    than the pass groups, so some are applied one by one), repeated pairs,
+    weights 1, 3 and 4, angles pi/2, -pi/2 and pi in random order; against the
+    oracle, bit for bit, on 20000 random strings over all 127 qubits."""
+    from workload.circuit import GateList, pauli_words
+    n = 127
+    rng = np.random.default_rng(77)
+    gens = []
+    for d in rng.choice(np.arange(1, n), 40, replace=False):
+        for _ in range(3):
+            a = int(rng.integers(0, n - int(d)))
+            gens.append(pauli_words(n, {a: "Z", a + int(d): "Z"}))
+    gens += [gens[i] for i in range(0, 30, 3)]  # repeated pairs
+    for wgt in (1, 1, 3, 3, 4, 4):
+        gens.append(pauli_words(n, {int(q): "Z" for q in rng.choice(n, wgt, replace=False)}))
+    angles = rng.choice([PI / 2, -PI / 2, PI], len(gens))
+    perm = rng.permutation(len(gens))
+    layer = GateList(np.stack(gens)[perm].astype(np.uint64), angles[perm][:, None].astype(np.float64))
+    terms, coeffs = w.random_pauli_set(n, 20000, seed=31)
+    say(f"clifford run of {len(layer)} mixed Z generators")
+    g = gpu_sum(n, terms, coeffs)
+    o = OracleSum(n, terms, coeffs)
+    g.apply_rotation_layer(layer)
+    o.apply(layer)
+    assert_same_operator(g, o, coeff_exact=True)
+    assert g.size() == len(terms)
+
+
 def test_empty_and_single_string():
     lat = w.heavy_hex_21()
     zz, rx = w.kicked_ising_step(lat, 0.6)
