@@ -397,11 +397,19 @@ __device__ __forceinline__ uint32_t acquire_tile(Ctrl* ctrl, uint32_t* s_tile) {
 // Exit protocol of every look-back kernel: the last workgroup to finish resets
 // the tile and done counters and advances the epoch.  Returns true in the one
 // thread that performs the reset (for extra end-of-launch bookkeeping).
+// Counts the workgroup done; the last one to finish gets true.  Every wave
+// first waits for its own memory operations to complete.  What a last
+// workgroup reads of the others' writes (the error bits, the maxima, the
+// output sizes) is written with agent-scope atomics, which complete at the
+// device's point of coherence, so that wait orders them before the count and
+// no device-scope fence is needed here: such a fence writes back and
+// invalidates the XCD's L2, and one per workgroup at the end of a launch
+// stalls every workgroup still running.
 __device__ __forceinline__ bool finish_launch(Ctrl* ctrl) {
+    __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     bool last = false;
     if (threadIdx.x == 0) {
-        __threadfence();
         const uint32_t d = atomicAdd(&ctrl->done_counter, 1u);
         if (d == gridDim.x - 1) {
             __threadfence();

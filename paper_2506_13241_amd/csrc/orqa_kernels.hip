@@ -102,37 +102,127 @@ __device__ __forceinline__ ulonglong2 shfl_u128(const ulonglong2& v, int src) {
 // block's first B position and its end.  One window of 128 keys around b
 // (one round trip to memory) settles any block that lies inside it, the
 // merge path included; wider blocks take 64-ary searches.
-__device__ TileDesc wave_split(const VIn& v, uint64_t n, uint64_t b) {
-    if (b >= n) return {n, n, n, n};
+// Ends of a pairing block wider than the split window (all 64 lanes, uniform
+// H): the block start hs = first i <= b - 64 with h(x_i) >= H when need_s
+// (the window's back half lies inside the block), and the block end he =
+// first i >= b + 64 with h(x_i) > H when need_e.  Lanes 0-31 look backwards
+// from b - 64 and lanes 32-63 forwards from b + 63, at 16 distances 32 apart
+// and then 16 doubling ones (one round trip for both ends), then each half
+// narrows its bracket by 32-ary search.
+__device__ void block_ends(const VIn& v, uint64_t n, uint64_t b, const ulonglong2& H, bool need_s, bool need_e,
+                           uint64_t& hs, uint64_t& he) {
     const int lane = lane_id();
-    // lane l reads positions b - 64 + l and b + l (lane 0's second key is b)
+    const bool fwd = lane >= 32;
+    const int l = lane & 31;
+    const bool need = fwd ? need_e : need_s;
+    auto dist = [](int j) { return j < 16 ? 32ull * uint64_t(j + 1) : (512ull << (j - 15)); };
+    // probe j of the back half is b - 64 - dist(j), of the front half b + 63 + dist(j);
+    // "outside" = before the block (back) or after it (front), positions
+    // beyond the operator included
+    bool out = true;
+    if (need) {
+        if (!fwd) {
+            const int64_t q = int64_t(b) - 64 - int64_t(dist(l));
+            out = q < 0 || k_lt(k_h(v.x(uint64_t(q))), H);
+        } else {
+            const uint64_t q = b + 63 + dist(l);
+            out = q >= n || k_lt(H, k_h(v.x(q)));
+        }
+    }
+    const uint64_t bal0 = __ballot(out);
+    const uint32_t ob = uint32_t(fwd ? (bal0 >> 32) : bal0);
+    // bracket [lo, hi): the answer is the first position in it where the
+    // predicate holds, hi if none (the predicate holds at hi)
+    uint64_t lo = 0, hi = 0;
+    if (need) {
+        const int L = ob ? __ffs(ob) - 1 : 32;  // first probe outside; 32: none
+        if (!fwd) {
+            const int64_t qin = L == 0 ? int64_t(b) - 64 : int64_t(b) - 64 - int64_t(dist(L - 1));
+            const int64_t qout = L < 32 ? int64_t(b) - 64 - int64_t(dist(L)) : -1;
+            lo = qout < 0 ? 0 : uint64_t(qout + 1);
+            hi = uint64_t(qin);
+        } else {
+            const uint64_t qin = L == 0 ? b + 63 : b + 63 + dist(L - 1);
+            const uint64_t qout = L < 32 ? b + 63 + dist(L) : n;
+            lo = qin + 1;
+            hi = qout < n ? qout : n;
+        }
+    }
+    for (;;) {
+        const bool act = need && lo < hi;
+        if (__ballot(act) == 0) break;
+        const uint64_t step = act ? (hi - lo + 31) >> 5 : 1;
+        const uint64_t q = lo + uint64_t(l + 1) * step - 1;
+        bool pr = false;
+        if (act) pr = q >= hi || (fwd ? k_lt(H, k_h(v.x(q))) : !k_lt(k_h(v.x(q)), H));
+        const uint64_t bal = __ballot(pr);
+        const uint32_t hb = uint32_t(fwd ? (bal >> 32) : bal);
+        if (act) {
+            if (hb == 0) {
+                lo = hi;
+            } else {
+                const uint64_t L2 = uint64_t(__ffs(hb) - 1);
+                const uint64_t qL = lo + (L2 + 1) * step - 1;
+                lo += L2 * step;
+                if (qL < hi) hi = qL;
+            }
+        }
+    }
+    const uint64_t r_s = __shfl(lo, 0), r_e = __shfl(lo, 32);
+    if (need_s) hs = r_s;
+    if (need_e) he = r_e;
+}
+
+struct SplitWin {
+    ulonglong2 xb, xf, zb, zf;  // lane l: keys at b - 64 + l and b + l (lane 0's second key is b)
+};
+
+__device__ __forceinline__ SplitWin split_window(const VIn& v, uint64_t n, uint64_t b) {
+    const int lane = lane_id();
     const int64_t pb = int64_t(b) - 64 + lane;
     const uint64_t pf = b + uint64_t(lane);
-    const ulonglong2 xb = pb >= 0 ? v.x(uint64_t(pb)) : make_ulonglong2(0, 0);
-    const ulonglong2 xf = pf < n ? v.x(pf) : make_ulonglong2(0, 0);
-    const ulonglong2 zb = pb >= 0 ? v.z(uint64_t(pb)) : make_ulonglong2(0, 0);
-    const ulonglong2 zf = pf < n ? v.z(pf) : make_ulonglong2(0, 0);
+    SplitWin w;
+    w.xb = pb >= 0 ? v.x(uint64_t(pb)) : make_ulonglong2(0, 0);
+    w.xf = pf < n ? v.x(pf) : make_ulonglong2(0, 0);
+    w.zb = pb >= 0 ? v.z(uint64_t(pb)) : make_ulonglong2(0, 0);
+    w.zf = pf < n ? v.z(pf) : make_ulonglong2(0, 0);
+    return w;
+}
+
+// b < n; W is split_window(v, n, b)
+__device__ TileDesc wave_split_win(const VIn& v, uint64_t n, uint64_t b, const SplitWin& W) {
+    const int lane = lane_id();
+    const int64_t pb = int64_t(b) - 64 + lane;
+    const uint64_t pf = b + uint64_t(lane);
+    const ulonglong2 xb = W.xb, xf = W.xf, zb = W.zb, zf = W.zf;
     const ulonglong2 H = k_h(shfl_u128(xf, 0));
     const ulonglong2 H1 = make_ulonglong2(H.x | 1ull, H.y);
     // block start: h is non-decreasing, so the lanes before the block form a prefix
     const uint64_t before = __ballot(pb < 0 || k_lt(k_h(xb), H));
-    const uint64_t hs = before != 0
-                            ? uint64_t(int64_t(b) - 64 + __popcll(before))
-                            : wave_lower_bound(0, b - 64, [&](uint64_t i) { return !k_lt(k_h(v.x(i)), H); });
     // block end (lane 0 reads b itself, which is inside)
     const uint64_t after = __ballot(pf >= n || k_lt(H, k_h(xf)));
-    const uint64_t he = after != 0
-                            ? b + uint64_t(__ffsll(static_cast<unsigned long long>(after)) - 1)
-                            : wave_lower_bound(b + 64, n, [&](uint64_t i) { return k_lt(H, k_h(v.x(i))); });
-    // first B string of the block
+    uint64_t hs = 0, he = 0;
+    if (before != 0) hs = uint64_t(int64_t(b) - 64 + __popcll(before));
+    if (after != 0) he = b + uint64_t(__ffsll(static_cast<unsigned long long>(after)) - 1);
+    if (before == 0 || after == 0) block_ends(v, n, b, H, before == 0, after == 0, hs, he);
+    // first B string of the block: exact when the window holds both an A and
+    // a B string of the block, else searched beyond the window's B (or A) part
+    const uint64_t mb = __ballot(pb >= int64_t(hs) && !k_lt(xb, H1));
+    const uint64_t mf = __ballot(pf < he && !k_lt(xf, H1));
+    const uint64_t ab = __ballot(pb >= int64_t(hs) && k_lt(xb, H1));
+    const uint64_t af = __ballot(pf < he && k_lt(xf, H1));
+    const bool hasB = (mb | mf) != 0, hasA = (ab | af) != 0;
+    uint64_t bfirst = he, alast = hs;  // first B and one past the last A in the window
+    if (hasB) bfirst = mb ? uint64_t(int64_t(b) - 64 + (__ffsll(static_cast<unsigned long long>(mb)) - 1))
+                          : b + uint64_t(__ffsll(static_cast<unsigned long long>(mf)) - 1);
+    if (hasA) alast = af ? b + uint64_t(63 - __clzll(af)) + 1
+                         : uint64_t(int64_t(b) - 64 + (63 - __clzll(ab))) + 1;
     uint64_t hm;
-    if (before != 0 && after != 0) {
-        const uint64_t mb = __ballot(pb >= int64_t(hs) && !k_lt(xb, H1));
-        const uint64_t mf = __ballot(pf < he && !k_lt(xf, H1));
-        hm = mb ? uint64_t(int64_t(b) - 64 + (__ffsll(static_cast<unsigned long long>(mb)) - 1))
-                : (mf ? b + uint64_t(__ffsll(static_cast<unsigned long long>(mf)) - 1) : he);
+    if ((before != 0 && after != 0) || (hasA && hasB)) {
+        hm = hasB ? bfirst : he;  // the window covers the A-to-B change
     } else {
-        hm = wave_lower_bound(hs, he, [&](uint64_t i) { return !k_lt(v.x(i), H1); });
+        hm = wave_lower_bound(hasA ? alast : hs, hasB ? bfirst : he,
+                              [&](uint64_t i) { return !k_lt(v.x(i), H1); });
     }
     const uint64_t na = hm - hs, nbb = he - hm, d = b - hs;
     // merge path: i = number of A strings among the first d merged
@@ -170,6 +260,11 @@ __device__ TileDesc wave_split(const VIn& v, uint64_t n, uint64_t b) {
     return {hs + i, hm + k, hm, he};
 }
 
+__device__ TileDesc wave_split(const VIn& v, uint64_t n, uint64_t b) {
+    if (b >= n) return {n, n, n, n};
+    return wave_split_win(v, n, b, split_window(v, n, b));
+}
+
 // Tile boundaries of an RX gate's input, found by the merge kernel itself
 // before it takes tiles: wave w of the grid finds boundaries w, w + W, ...
 // (W waves), the split of merged position t kRxTile for t = 0 .. ntiles (the
@@ -183,9 +278,17 @@ struct TileDescWords {
 __device__ __forceinline__ void rx_boundaries(const VIn& v, uint64_t n, TileDescWords* desc, uint32_t ep) {
     const uint64_t ntiles = (n + kRxTile - 1) / kRxTile;
     const uint64_t waves = uint64_t(gridDim.x) * (kThreads / 64);
-    for (uint64_t t = blockIdx.x * uint64_t(kThreads / 64) + (threadIdx.x >> 6); t <= ntiles; t += waves) {
-        const uint64_t b = t * kRxTile;
-        const TileDesc d = wave_split(v, n, b < n ? b : n);
+    uint64_t t = blockIdx.x * uint64_t(kThreads / 64) + (threadIdx.x >> 6);
+    if (t > ntiles) return;
+    // the window of the wave's next boundary is in flight while this one is settled
+    SplitWin w = split_window(v, n, t * kRxTile < n ? t * kRxTile : n);
+    for (; t <= ntiles; t += waves) {
+        const uint64_t b = t * kRxTile < n ? t * kRxTile : n;
+        const uint64_t tn = t + waves;
+        SplitWin wn = w;
+        if (tn <= ntiles) wn = split_window(v, n, tn * kRxTile < n ? tn * kRxTile : n);
+        const TileDesc d = b < n ? wave_split_win(v, n, b, w) : TileDesc{n, n, n, n};
+        w = wn;
         const int lane = lane_id();
         if (lane < 4) {
             const uint64_t val = lane == 0 ? d.posA : lane == 1 ? d.posB : lane == 2 ? d.hm : d.he;
@@ -596,8 +699,8 @@ __device__ __forceinline__ void rx_merge_body(const RxArgs& A, const GateTrig& g
                     atomicMax(reinterpret_cast<unsigned long long*>(&ctrl->need),
                               static_cast<unsigned long long>(tf + tb));
                 } else {
-                    ctrl->nf[A.out_buf] = tf;
-                    ctrl->nb[A.out_buf] = tb;
+                    st_rel(&ctrl->nf[A.out_buf], tf);  // read by the launch's last workgroup
+                    st_rel(&ctrl->nb[A.out_buf], tb);
                 }
             }
 #pragma unroll
@@ -661,8 +764,8 @@ __device__ __forceinline__ void rx_merge_body(const RxArgs& A, const GateTrig& g
                     atomicMax(reinterpret_cast<unsigned long long*>(&ctrl->need),
                               static_cast<unsigned long long>(tf + tb));
                 } else {
-                    ctrl->nf[A.out_buf] = tf;
-                    ctrl->nb[A.out_buf] = tb;
+                    st_rel(&ctrl->nf[A.out_buf], tf);  // read by the launch's last workgroup
+                    st_rel(&ctrl->nb[A.out_buf], tb);
                 }
             }
 #pragma unroll 1
@@ -734,14 +837,17 @@ __device__ __forceinline__ void rx_merge_body(const RxArgs& A, const GateTrig& g
         // a failed stage keeps its input (and the input's max) for the re-run
         if (__hip_atomic_load(&ctrl->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u) {
             for (int a = 0; a < kMaxLanes; ++a) ctrl->maxbits[A.mx_in][a] = 0ull;
+            uint64_t n_out = 0;
             if (ntiles == 0) {
                 ctrl->nf[A.out_buf] = 0;
                 ctrl->nb[A.out_buf] = 0;
+            } else {
+                n_out = ld_acq(&ctrl->nf[A.out_buf]) + ld_acq(&ctrl->nb[A.out_buf]);
             }
             ctrl->stages_done += 1;
             ctrl->cnt_updates += n;
             ctrl->cnt_rx_in += n;
-            ctrl->cnt_rx_out += ctrl->nf[A.out_buf] + ctrl->nb[A.out_buf];
+            ctrl->cnt_rx_out += n_out;
             ctrl->cnt_rx_launches += 1;
         }
     }
@@ -861,12 +967,12 @@ __global__ __launch_bounds__(kThreads) void k_compact(CompactArgs A) {
                     for (int a = 0; a < LP; ++a) keepL |= absd(cs[k][a]) * gw > sThrL[a];
                     al = al && keepL;
                 }
-                gs = (i == 0);
-                if (!gs) {
-                    const ulonglong2 xp = A.Xin[vphys(i - 1, nf, A.cap)];
-                    gs = !k_eq(xp, xs[k]);
-                }
             }
+            // a group starts where x differs from the string before (the lane
+            // before holds it; lane 0 reads it)
+            ulonglong2 xp = shfl_u128(xs[k], lane > 0 ? lane - 1 : 0);
+            if (lane == 0 && i < n && i > 0) xp = A.Xin[vphys(i - 1, nf, A.cap)];
+            if (i < n) gs = (i == 0) || !k_eq(xp, xs[k]);
             balA[k] = __ballot(al);
             balG[k] = __ballot(gs);
         }
@@ -889,9 +995,9 @@ __global__ __launch_bounds__(kThreads) void k_compact(CompactArgs A) {
         uint64_t oW = sBase[0] + (wOff & 0xFFFFu);  // survivors before element k of this wave
         uint64_t rW = sBase[1] + (wOff >> 16);      // group starts before element k of this wave
         if (tile == ntiles - 1 && tid == 0) {
-            ctrl->nf[A.out_buf] = sBase[0] + (totPacked & 0xFFFFu);
-            ctrl->nb[A.out_buf] = 0;
-            if (!A.prefix_only) ctrl->nranks = sBase[1] + (totPacked >> 16);
+            st_rel(&ctrl->nf[A.out_buf], sBase[0] + (totPacked & 0xFFFFu));  // read by the last workgroup
+            st_rel(&ctrl->nb[A.out_buf], 0ull);
+            if (!A.prefix_only) st_rel(&ctrl->nranks, sBase[1] + (totPacked >> 16));
         }
 #pragma unroll
         for (int k = 0; k < kCompactIPT; ++k) {
@@ -1327,47 +1433,49 @@ hipError_t launch_sort_hist(Ctrl* ctrl, int buf, const uint32_t* R, const ulongl
 // sort (the input is left untouched).
 
 // The groups a tile owns: [a, b) from the first group start at or after t0 to
-// the first at or after t1 (or n), found one chunk of kGsThreads positions at
-// a time.  Returns 0 when no group starts in the tile, -1 when a group is
-// longer than kGsMaxGroup (ctrl->aux[2] is set), 1 otherwise.  Called by the
-// whole workgroup.
+// the first at or after t1 (or n): wave 0 looks from t0 and wave 1 from t1,
+// 64 positions per step (a string's predecessor from the lane before it).
+// Returns 0 when no group starts in the tile, -1 when a group is longer than
+// kGsMaxGroup (ctrl->aux[2] is set), 1 otherwise.  Called by the whole
+// workgroup.
 __device__ int gs_tile_groups(const GroupSortArgs& A, uint64_t n, uint64_t t0, uint64_t t1, uint32_t& sA,
                               uint32_t& sB, uint64_t& a, uint64_t& b) {
-    const int tid = threadIdx.x;
-    if (tid == 0) {
-        sA = 0xFFFFFFFFu;
-        sB = 0xFFFFFFFFu;
+    const int wave = threadIdx.x >> 6, lane = lane_id();
+    if (wave < 2) {
+        const uint64_t base = wave == 0 ? t0 : t1;
+        uint32_t found = 0xFFFFFFFFu;
+        for (uint32_t c = 0; base < n && c < uint32_t(kGsMaxGroup); c += 64) {
+            const uint64_t p = base + c + uint64_t(lane);
+            const bool in = p < n;
+            const ulonglong2 x = in ? A.Xs[p] : make_ulonglong2(0, 0);
+            ulonglong2 prev = shfl_u128(x, lane > 0 ? lane - 1 : 0);
+            if (lane == 0 && in && p > 0) prev = A.Xs[p - 1];
+            const uint64_t st = __ballot(in && (p == 0 || !k_eq(x, prev)));
+            if (st) {
+                found = c + uint32_t(__ffsll(static_cast<unsigned long long>(st)) - 1);
+                break;
+            }
+            if (base + c + 64 >= n) break;
+        }
+        if (lane == 0) {
+            if (wave == 0) sA = found;
+            else sB = found;
+        }
     }
     __syncthreads();
-    for (int c = 0; c < kGsMaxGroup; c += kGsThreads) {
-        const int i = c + tid;
-        const uint64_t p = t0 + i, q = t1 + i;
-        if (i < kGsMaxGroup) {
-            if (p < n && (p == 0 || !k_eq(A.Xs[p], A.Xs[p - 1]))) atomicMin(&sA, uint32_t(i));
-            if (q < n && !k_eq(A.Xs[q], A.Xs[q - 1])) atomicMin(&sB, uint32_t(i));
-        }
-        __syncthreads();
-        const uint64_t next = uint64_t(c) + kGsThreads;
-        const bool doneA = sA != 0xFFFFFFFFu || t0 + next >= n;
-        const bool doneB = t1 >= n || sB != 0xFFFFFFFFu || t1 + next >= n;
-        __syncthreads();  // every thread has read sA and sB before the next chunk updates them
-        if (doneA && doneB) break;
-    }
     // A search window of full length without a group start means a group
     // longer than kGsMaxGroup; one cut short by the end of the operator only
     // means that no group starts there.
     const bool full_a = t0 + kGsMaxGroup <= n, full_b = t1 + kGsMaxGroup <= n;
     const bool over = (sA == 0xFFFFFFFFu && full_a) || (t1 < n && sB == 0xFFFFFFFFu && full_b);
-    if (over) {
-        if (tid == 0) atomicOr(reinterpret_cast<unsigned int*>(&A.ctrl->aux[2]), 1u);
-        __syncthreads();
-        return -1;
-    }
     a = sA == 0xFFFFFFFFu ? n : t0 + sA;
     b = (t1 < n && sB != 0xFFFFFFFFu) ? t1 + sB : n;
-    const int own = a < t1 ? 1 : 0;  // else the tile's strings belong to an earlier tile's group
-    __syncthreads();                 // sA, sB read by every thread before the next tile resets them
-    return own;
+    __syncthreads();  // sA, sB read by every thread before the next tile sets them
+    if (over) {
+        if (threadIdx.x == 0) atomicOr(reinterpret_cast<unsigned int*>(&A.ctrl->aux[2]), 1u);
+        return -1;
+    }
+    return a < t1 ? 1 : 0;  // else the tile's strings belong to an earlier tile's group
 }
 
 // Any group order: a string's new position is its group's start plus the
@@ -1490,22 +1598,35 @@ __global__ __launch_bounds__(kGsThreads, 4) void k_group_sort_xor(GroupSortArgs 
         if (gs_tile_groups(A, n, t0, t1, sA, sB, a, b) <= 0) continue;
         const uint32_t m = uint32_t(b - a);  // <= kGsCap by construction
         // the coefficients stay in registers until the write; x and z are read
-        // again there (the tile's strings are still in the cache)
+        // again there (the tile's strings are still in the cache).  A string's
+        // predecessor is the lane before it (lane 0 reads its own).
         constexpr bool kRegC = LP * sizeof(CT) <= 16;
         CT cr[kGsIPT][kRegC ? LP : 1];
         uint32_t swap = 0;  // bit k: the pair ending at element k swaps its node
+        const int lane = lane_id();
+        if constexpr (kRegC) {
 #pragma unroll
-        for (int k = 0; k < kGsIPT; ++k) {
-            const uint32_t e = k * kGsThreads + tid;
-            const uint64_t p = a + (e < m ? e : 0u);
-            if constexpr (kRegC) {
+            for (int k = 0; k < kGsIPT; ++k) {
+                const uint32_t e = k * kGsThreads + tid;
+                const uint64_t p = a + (e < m ? e : 0u);
 #pragma unroll
                 for (int l = 0; l < LP; ++l) cr[k][l] = Cs[p * LP + l];
             }
+        }
+#pragma unroll 1
+        for (int k = 0; k < kGsIPT; ++k) {
+            const uint32_t e = k * kGsThreads + tid;
+            if (__ballot(e < m) == 0) break;  // e grows with k
+            const uint64_t p = a + (e < m ? e : 0u);
+            const ulonglong2 x = A.Xs[p], z = A.Zs[p];
+            ulonglong2 xp = shfl_u128(x, lane > 0 ? lane - 1 : 0), zp = shfl_u128(z, lane > 0 ? lane - 1 : 0);
+            if (lane == 0 && e != 0 && e < m) {
+                xp = A.Xs[p - 1];
+                zp = A.Zs[p - 1];
+            }
             if (e < m) {
                 uint8_t d = kTop;
-                if (e != 0 && k_eq(A.Xs[p], A.Xs[p - 1])) {
-                    const ulonglong2 z = A.Zs[p], zp = A.Zs[p - 1];
+                if (e != 0 && k_eq(x, xp)) {
                     d = uint8_t(hdb128(make_ulonglong2(zp.x ^ z.x, zp.y ^ z.y)));
                     swap |= uint32_t(k_lt(z, zp)) << k;
                 }
