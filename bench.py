@@ -303,6 +303,22 @@ def main():
         "run_merges": int(st["run_merges"]),
         "paper_time_per_gate_ms": round(dt / args.steps / 271 * 1e3, 4),
     }
+    if st["radix_sorts"] == 0 and st["sort_passes"] == st["cliff_launches"] and st["cliff_ms"] > 0 \
+            and st["sort_ms"] > 0:
+        # one Clifford pass (reads cliff_in strings, writes its survivors with
+        # their 4-byte group rank) and one in-group re-sort (reads and writes
+        # the survivors) per step
+        n_cl_out = st["sort_elems"]
+        cl_bytes = st["cliff_in"] * bps + n_cl_out * (bps + 4)
+        gs_bytes = 2 * n_cl_out * bps
+        for name, kern, b, ms, launches in (("clifford", "k_compact", cl_bytes, st["cliff_ms"], st["cliff_launches"]),
+                                            ("group_sort", "k_group_sort_xor", gs_bytes, st["sort_ms"],
+                                             st["sort_passes"])):
+            gbs = b / (ms * 1e-3) / 1e9
+            extra[name] = {"kernel": kern, "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                           "frac": round(gbs / HBM_PEAK_GBS, 4), "launches": int(launches),
+                           "mean_launch_ms": round(ms / max(launches, 1), 4),
+                           "algorithmic_bytes_per_launch": round(b / max(launches, 1))}
     if lanes > 1:
         extra["lanes"] = lanes
         extra["string_lane_updates_per_s"] = updates * lanes / dt

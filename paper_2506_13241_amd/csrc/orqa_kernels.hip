@@ -1568,6 +1568,14 @@ __global__ __launch_bounds__(kGsThreads) void k_group_sort(GroupSortArgs A) {
 // of all nodes meet in a difference array whose prefix sum is each string's
 // displacement inside its group: O(depth of the trie) work per string in
 // place of a scan of its whole group.
+// High bit of every byte of w (eight entries of D, each <= 126 or 0xFF) that
+// is greater than d <= 126: (b | 0x80) - (d + 1) keeps its high bit exactly
+// when b & 0x7F > d, and no byte borrows from the next.
+__device__ __forceinline__ uint64_t bytes_above(uint64_t w, uint32_t d) {
+    constexpr uint64_t kHi = 0x8080808080808080ull, kOne = 0x0101010101010101ull;
+    return ((w | kHi) - kOne * uint64_t(d + 1u)) & kHi;
+}
+
 __device__ __forceinline__ uint32_t hdb128(const ulonglong2& t) {  // t != 0
     return t.y ? 127u - uint32_t(__clzll(t.y)) : 63u - uint32_t(__clzll(t.x));
 }
@@ -1577,6 +1585,7 @@ __global__ __launch_bounds__(kGsThreads, 4) void k_group_sort_xor(GroupSortArgs 
     constexpr int kPad = kGsCap + 64;
     constexpr uint8_t kTop = 0xFF;                   // group start, and every entry from m on
     __shared__ __align__(16) uint8_t sD[kPad];        // D_e
+    const uint64_t* sW = reinterpret_cast<const uint64_t*>(sD);
     __shared__ uint8_t sBM[kPad / 32];               // maxima of sD over 32-entry blocks
     __shared__ uint32_t sDiff[kGsCap + 1];           // displacements (two's complement)
     __shared__ uint32_t sWave[kGsThreads / 64];
@@ -1648,30 +1657,43 @@ __global__ __launch_bounds__(kGsThreads, 4) void k_group_sort_xor(GroupSortArgs 
             sBM[j] = uint8_t(mx);
         }
         __syncthreads();
-#pragma unroll
+#pragma unroll 1
         for (int k = 0; k < kGsIPT; ++k) {
             if (!((swap >> k) & 1u)) continue;
             const int e = k * kGsThreads + tid;
             const uint8_t d = sD[e];
-            // PG: sD[gs] = kTop > d bounds the walk to the left
-            int pg = e - 1;
-            const int lo = pg & ~31;
-            while (pg >= lo && sD[pg] <= d) --pg;
-            if (pg < lo) {
-                int blk = (lo >> 5) - 1;
-                while (sBM[blk] <= d) --blk;
-                pg = blk * 32 + 31;
-                while (sD[pg] <= d) --pg;
+            // PG: sD[gs] = kTop > d bounds the walk to the left; 8 entries per
+            // read, then 32-entry block maxima
+            int pg;
+            {
+                int wi = (e - 1) >> 3;
+                const int bi = (e - 1) & 7;
+                uint64_t hit = bytes_above(sW[wi], d) & (bi == 7 ? ~0ull : ((1ull << (8 * (bi + 1))) - 1ull));
+                const int wlo = wi & ~3;
+                while (!hit && wi > wlo) hit = bytes_above(sW[--wi], d);
+                if (!hit) {
+                    int blk = (wi >> 2) - 1;
+                    while (sBM[blk] <= d) --blk;
+                    wi = blk * 4 + 3;
+                    while (!(hit = bytes_above(sW[wi], d))) --wi;
+                }
+                pg = wi * 8 + ((63 - __clzll(hit)) >> 3);
             }
             // NG: sD[m] = kTop bounds the walk to the right
-            int ng = e + 1;
-            const int hi = ng | 31;
-            while (ng <= hi && sD[ng] <= d) ++ng;
-            if (ng > hi) {
-                int blk = (hi >> 5) + 1;
-                while (sBM[blk] <= d) ++blk;
-                ng = blk * 32;
-                while (sD[ng] <= d) ++ng;
+            int ng;
+            {
+                int wi = (e + 1) >> 3;
+                const int bi = (e + 1) & 7;
+                uint64_t hit = bytes_above(sW[wi], d) & ~((1ull << (8 * bi)) - 1ull);
+                const int whi = wi | 3;
+                while (!hit && wi < whi) hit = bytes_above(sW[++wi], d);
+                if (!hit) {
+                    int blk = (wi >> 2) + 1;
+                    while (sBM[blk] <= d) ++blk;
+                    wi = blk * 4;
+                    while (!(hit = bytes_above(sW[wi], d))) ++wi;
+                }
+                ng = wi * 8 + (__ffsll(static_cast<unsigned long long>(hit)) - 1) / 8;
             }
             const uint32_t R = uint32_t(ng - e), L = uint32_t(e - pg);
             atomicAdd(&sDiff[pg], R);
