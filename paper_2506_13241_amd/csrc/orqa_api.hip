@@ -546,7 +546,7 @@ void group_cliff_gens(const std::vector<CliffGen>& gens, std::vector<CliffGroup>
 
 int enqueue_compact(ps_handle* h, int in, int out, int mx_in, int mx_out, double eps_in, const CliffGen* gens,
                     int ngens, bool with_rank, int gate_count = 0, double eps_learned = -1.0,
-                    const CliffGroup* groups = nullptr, int ngroups = 0) {
+                    const CliffGroup* groups = nullptr, int ngroups = 0, bool groups_neg_is_k = false) {
     const bool learned = eps_learned > 0.0;
     if (learned) {  // score every input string, then the compaction applies the learned rule
         ScorerFwdArgs f{};
@@ -592,6 +592,7 @@ int enqueue_compact(ps_handle* h, int in, int out, int mx_in, int mx_out, double
     a.ngens = ngens;
     a.groups = groups;
     a.ngroups = ngroups;
+    a.groups_neg_is_k = groups_neg_is_k ? 1 : 0;
     a.gate_count = gate_count;
     a.gscore = learned ? h->gscore : nullptr;
     a.eps_learned = learned ? eps_learned : 0.0;
@@ -1567,8 +1568,11 @@ int apply_rotation_layer(ps_handle* h, const ps_pauli* gens, const double* theta
                 if (!groups.empty())
                     HIP_TRY(hipMemcpyAsync(dgroups, groups.data(), groups.size() * sizeof(CliffGroup),
                                            hipMemcpyHostToDevice, h->stream));
+                bool neg_is_k = true;  // e.g. every generator at theta = -pi/2
+                for (const CliffGroup& c : groups) neg_is_k = neg_is_k && c.k0 == c.n0 && c.k1 == c.n1;
                 rc = enqueue_compact(h, in, out, mx_in, mx_out, h->pend, h->cgens, int(rest.size()),
-                                     s.needs_sort, int(s.gate_count), eps_learned, dgroups, int(groups.size()));
+                                     s.needs_sort, int(s.gate_count), eps_learned, dgroups, int(groups.size()),
+                                     neg_is_k);
                 if (rc) return rc;
                 if (!s.gens.empty()) HIP_TRY(hipStreamSynchronize(h->stream));  // cgens reused by the next run
             }

@@ -126,14 +126,18 @@ __device__ __forceinline__ uint32_t st_flag(uint64_t s, uint32_t ep) {
 // exclusive prefix of `tile` (uniform).  Publishes the aggregate first, so a
 // tile never waits before its own aggregate is visible: every wait ends once
 // the earlier tiles (which took their indices first) publish theirs.
-__device__ __forceinline__ uint64_t lookback_wave(uint64_t* st, uint64_t stride, uint32_t tile, uint32_t ep, uint64_t agg,
-                                  uint32_t* err) {
+// In two halves, so that a workgroup can publish a tile's aggregate, do other
+// work and resolve the prefix later (each called by all 64 lanes of one
+// wave; the aggregate is published before any wait, so every wait ends).
+__device__ __forceinline__ void lookback_publish(uint64_t* st, uint64_t stride, uint32_t tile, uint32_t ep,
+                                                 uint64_t agg) {
+    if (lane_id() == 0) st_rel(st + tile * stride, st_pack(ep, tile == 0 ? 2u : 1u, agg));
+}
+
+__device__ __forceinline__ uint64_t lookback_resolve(uint64_t* st, uint64_t stride, uint32_t tile, uint32_t ep,
+                                                     uint64_t agg, uint32_t* err) {
     const int lane = lane_id();
-    if (tile == 0) {
-        if (lane == 0) st_rel(st, st_pack(ep, 2, agg));
-        return 0;
-    }
-    if (lane == 0) st_rel(st + tile * stride, st_pack(ep, 1, agg));
+    if (tile == 0) return 0;
     uint64_t excl = 0;
     int64_t base = static_cast<int64_t>(tile) - 1;
     const uint64_t t0 = wall_clock64();
@@ -192,6 +196,12 @@ __device__ __forceinline__ uint64_t lookback_wave(uint64_t* st, uint64_t stride,
     }
     if (lane == 0) st_rel(st + tile * stride, st_pack(ep, 2, excl + agg));
     return excl;
+}
+
+__device__ __forceinline__ uint64_t lookback_wave(uint64_t* st, uint64_t stride, uint32_t tile, uint32_t ep, uint64_t agg,
+                                                  uint32_t* err) {
+    lookback_publish(st, stride, tile, ep, agg);
+    return lookback_resolve(st, stride, tile, ep, agg, err);
 }
 
 // Back-off between polls of the two-level look-back, in units of 64 clocks.

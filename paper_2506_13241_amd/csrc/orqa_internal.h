@@ -142,6 +142,7 @@ struct CompactArgs {
     int ngens;
     const CliffGroup* groups;  // weight-2 generators by qubit offset
     int ngroups;
+    int groups_neg_is_k;       // every group's n masks equal its k masks
     int gate_count;      // gates this pass stands for (measurement counters)
     const float* gscore;  // learned truncation: log10 predicted weight per input string, or null
     double eps_learned;

@@ -984,11 +984,56 @@ __global__ __launch_bounds__(kThreads) void k_compact(CompactArgs A) {
         }
         uint32_t totPacked;
         const uint32_t wOff = __shfl(block_excl_scan(lane == 0 ? (nal | (ngs << 16)) : 0u, sWave, totPacked), 0);
+        // publish this tile's counts first, then apply the run's product to the
+        // surviving strings (zs[k] becomes z_f; negs bit k: the product
+        // negates it) while the predecessors' prefixes arrive
+        if (wave == 0) lookback_publish(A.status, 1, tile, ep, totPacked & 0xFFFFu);
+        else if (wave == 1) lookback_publish(A.status + A.max_tiles, 1, tile, ep, totPacked >> 16);
+        uint32_t negs = 0;
+        if (cliff) {
+#pragma unroll
+            for (int k = 0; k < kCompactIPT; ++k) {
+                if (!((balA[k] >> lane) & 1ull)) continue;
+                ulonglong2 z = zs[k];
+                bool neg = false;
+                {
+                    const ulonglong2 x = rotl_n(xs[k], A.xrot, A.nq);
+                    int K = 0, nneg = 0;
+                    for (int gi = 0; gi < A.ngroups; ++gi) {
+                        // bit a of c: x_a != x_(a+d), i.e. Z_a Z_(a+d) anticommutes
+                        const uint32_t d = __builtin_amdgcn_readfirstlane(sGrp[gi].d);
+                        const ulonglong2 y = shr128(x, d);
+                        const uint64_t c0 = x.x ^ y.x, c1 = x.y ^ y.y;
+                        const ulonglong2 ck = make_ulonglong2(c0 & sGrp[gi].k0, c1 & sGrp[gi].k1);
+                        const ulonglong2 up = shl128(ck, d);
+                        z.x ^= ck.x ^ up.x;
+                        z.y ^= ck.y ^ up.y;
+                        K += __popcll(ck.x) + __popcll(ck.y);
+                        if (!A.groups_neg_is_k) nneg += __popcll(c0 & sGrp[gi].n0) + __popcll(c1 & sGrp[gi].n1);
+                    }
+                    if (A.groups_neg_is_k) nneg = K;  // every grouped generator with sin = -1
+                    for (int gi = 0; gi < A.ngens; ++gi) {
+                        const CliffGen G = sG[gi];
+                        if (!((__popcll(x.x & G.z0) + __popcll(x.y & G.z1)) & 1)) continue;
+                        if (G.kodd) {
+                            z.x ^= G.z0;
+                            z.y ^= G.z1;
+                            ++K;
+                        }
+                        nneg += int(G.neg);
+                    }
+                    const int e = k_popc_and(x, z) - k_popc_and(x, zs[k]) + K;  // even
+                    neg = ((e & 3) == 2) != ((nneg & 1) != 0);
+                }
+                negs |= uint32_t(neg) << k;
+                zs[k] = z;
+            }
+        }
         if (wave == 0) {
-            const uint64_t b = lookback_wave(A.status, 1, tile, ep, totPacked & 0xFFFFu, &ctrl->err);
+            const uint64_t b = lookback_resolve(A.status, 1, tile, ep, totPacked & 0xFFFFu, &ctrl->err);
             if (lane_id() == 0) sBase[0] = b;
         } else if (wave == 1) {
-            const uint64_t b = lookback_wave(A.status + A.max_tiles, 1, tile, ep, totPacked >> 16, &ctrl->err);
+            const uint64_t b = lookback_resolve(A.status + A.max_tiles, 1, tile, ep, totPacked >> 16, &ctrl->err);
             if (lane_id() == 0) sBase[1] = b;
         }
         __syncthreads();
@@ -1006,36 +1051,8 @@ __global__ __launch_bounds__(kThreads) void k_compact(CompactArgs A) {
             oW += uint64_t(__popcll(balA[k]));
             rW += uint64_t(__popcll(balG[k]));
             if (!((balA[k] >> lane) & 1ull)) continue;
-            ulonglong2 z = zs[k];
-            bool neg = false;
-            if (cliff) {
-                const ulonglong2 x = rotl_n(xs[k], A.xrot, A.nq);
-                int K = 0, nneg = 0;
-                for (int gi = 0; gi < A.ngroups; ++gi) {
-                    // bit a of c: x_a != x_(a+d), i.e. Z_a Z_(a+d) anticommutes
-                    const uint32_t d = __builtin_amdgcn_readfirstlane(sGrp[gi].d);
-                    const ulonglong2 y = shr128(x, d);
-                    const uint64_t c0 = x.x ^ y.x, c1 = x.y ^ y.y;
-                    const ulonglong2 ck = make_ulonglong2(c0 & sGrp[gi].k0, c1 & sGrp[gi].k1);
-                    const ulonglong2 up = shl128(ck, d);
-                    z.x ^= ck.x ^ up.x;
-                    z.y ^= ck.y ^ up.y;
-                    K += __popcll(ck.x) + __popcll(ck.y);
-                    nneg += __popcll(c0 & sGrp[gi].n0) + __popcll(c1 & sGrp[gi].n1);
-                }
-                for (int gi = 0; gi < A.ngens; ++gi) {
-                    const CliffGen G = sG[gi];
-                    if (!((__popcll(x.x & G.z0) + __popcll(x.y & G.z1)) & 1)) continue;
-                    if (G.kodd) {
-                        z.x ^= G.z0;
-                        z.y ^= G.z1;
-                        ++K;
-                    }
-                    nneg += int(G.neg);
-                }
-                const int e = k_popc_and(x, z) - k_popc_and(x, zs[k]) + K;  // even
-                neg = ((e & 3) == 2) != ((nneg & 1) != 0);
-            }
+            const bool neg = (negs >> k) & 1u;
+            const ulonglong2 z = zs[k];
             A.Xout[o] = xs[k];
             A.Zout[o] = z;
             if (A.rank_out) A.rank_out[o] = uint32_t(rk - 1);
