@@ -822,17 +822,24 @@ __device__ __forceinline__ void rx_merge_body(const RxArgs& A, const GateTrig& g
     }
 
     // ---- per-lane max of the outputs (wider rows: lane q kVPC + j is held by
-    // the threads whose chunk is q, i.e. lane index q modulo kCPR)
+    // the threads whose chunk is q, i.e. lane index q modulo kCPR), over the
+    // waves through LDS, then one atomic per lane and workgroup: the
+    // workgroups leave within a few microseconds of each other, and atomics
+    // on one word from all of them queue behind each other
+    __shared__ unsigned long long sWmax[LP];  // bit patterns of non-negative doubles order like the values
+    if (tid < LP) sWmax[tid] = 0ull;
+    __syncthreads();
 #pragma unroll
     for (int j = 0; j < kVPC; ++j) {
         double mx = vmax[j];
 #pragma unroll
         for (int o = kCPR; o < 64; o <<= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
         const int q = lane_id();
-        if (q < kCPR && mx > 0.0)
-            atomicMax(reinterpret_cast<unsigned long long*>(&ctrl->maxbits[A.mx_out][q * kVPC + j]),
-                      static_cast<unsigned long long>(d_to_bits(mx)));
+        if (q < kCPR && mx > 0.0) atomicMax(&sWmax[q * kVPC + j], static_cast<unsigned long long>(d_to_bits(mx)));
     }
+    __syncthreads();
+    if (tid < LP && sWmax[tid] != 0ull)
+        atomicMax(reinterpret_cast<unsigned long long*>(&ctrl->maxbits[A.mx_out][tid]), sWmax[tid]);
     if (finish_launch(ctrl)) {
         // a failed stage keeps its input (and the input's max) for the re-run
         if (__hip_atomic_load(&ctrl->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u) {
@@ -1065,14 +1072,18 @@ __global__ __launch_bounds__(kThreads) void k_compact(CompactArgs A) {
         }
         __syncthreads();
     }
-    if (!A.prefix_only) {
+    if (!A.prefix_only) {  // over the waves through LDS, then one atomic per lane and workgroup
+        __shared__ unsigned long long sWmax[LP];
+        if (tid < LP) sWmax[tid] = 0ull;
+        __syncthreads();
 #pragma unroll
         for (int a = 0; a < LP; ++a) {
             const double mx = wave_max_d(vmax[a]);
-            if (lane_id() == 0 && mx > 0.0)
-                atomicMax(reinterpret_cast<unsigned long long*>(&ctrl->maxbits[A.mx_out][a]),
-                          static_cast<unsigned long long>(d_to_bits(mx)));
+            if (lane_id() == 0 && mx > 0.0) atomicMax(&sWmax[a], static_cast<unsigned long long>(d_to_bits(mx)));
         }
+        __syncthreads();
+        if (tid < LP && sWmax[tid] != 0ull)
+            atomicMax(reinterpret_cast<unsigned long long*>(&ctrl->maxbits[A.mx_out][tid]), sWmax[tid]);
     }
     if (finish_launch(ctrl)) {
         if (A.prefix_only) {
