@@ -15,7 +15,9 @@ namespace orqa {
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
-__device__ __forceinline__ uint16_t f2bf(float f) { return scorer_bf16(f); }  // round to nearest even
+// round to nearest even: the same bits as scorer_bf16 for finite values, in
+// one instruction (v_cvt_pk_bf16_f32)
+__device__ __forceinline__ uint16_t f2bf(float f) { return __builtin_bit_cast(uint16_t, static_cast<__bf16>(f)); }
 __device__ __forceinline__ float bf2f(uint16_t b) { return __uint_as_float(static_cast<uint32_t>(b) << 16); }
 
 // erf by Hastings' rational approximation (Abramowitz & Stegun, Handbook of
@@ -24,13 +26,24 @@ __device__ __forceinline__ float bf2f(uint16_t b) { return __uint_as_float(stati
 // far below the bf16 rounding the activations get next.  Branch-free: one
 // exponential and one reciprocal instead of a piecewise polynomial.
 __device__ __forceinline__ float erf_as(float x) {
+    // fused multiply-adds written out: the library builds without contraction
+    // (the merge's products and sums must round as written), the scorer does not
     const float u = fabsf(x);
-    const float t = __frcp_rn(1.0f + 0.3275911f * u);
-    const float poly = t * (0.254829592f + t * (-0.284496736f + t * (1.421413741f + t * (-1.453152027f + t * 1.061405429f))));
-    const float e = 1.0f - poly * __expf(-u * u);
+    // the hardware reciprocal (about one ulp) is far inside the formula's own
+    // error; a correctly rounded one costs the whole division sequence
+    const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f, u, 1.0f));
+    float p = fmaf(t, 1.061405429f, -1.453152027f);
+    p = fmaf(t, p, 1.421413741f);
+    p = fmaf(t, p, -0.284496736f);
+    p = fmaf(t, p, 0.254829592f);
+    p *= t;
+    const float e = fmaf(-p, __expf(-u * u), 1.0f);
     return copysignf(e, x);
 }
-__device__ __forceinline__ float gelu(float x) { return 0.5f * x * (1.0f + erf_as(x * 0.70710678118654752f)); }
+__device__ __forceinline__ float gelu(float x) {
+    const float h = 0.5f * x;
+    return fmaf(h, erf_as(x * 0.70710678118654752f), h);
+}
 __device__ __forceinline__ float gelu_grad(float x) {
     const float cdf = 0.5f * (1.0f + erf_as(x * 0.70710678118654752f));
     const float pdf = 0.3989422804014327f * __expf(-0.5f * x * x);
@@ -41,12 +54,11 @@ __device__ __forceinline__ float gelu_grad(float x) {
 // times scale[f].  Letters: 0 X, 1 Y, 2 Z, 3 any non-identity.
 __device__ __forceinline__ float feature(const ulonglong2& mx, const ulonglong2& my, const ulonglong2& mz,
                                          const ulonglong2& ma, const ulonglong2& q, uint32_t letter, float scale) {
-    // branch-free select of the letter mask (a select chain over the four
-    // masks would be lowered to an indexed private array)
-    const uint64_t s0 = 0ull - uint64_t(letter == 0), s1 = 0ull - uint64_t(letter == 1);
-    const uint64_t s2 = 0ull - uint64_t(letter == 2), s3 = 0ull - uint64_t(letter == 3);
-    const uint64_t lo = (mx.x & s0) | (my.x & s1) | (mz.x & s2) | (ma.x & s3);
-    const uint64_t hi = (mx.y & s0) | (my.y & s1) | (mz.y & s2) | (ma.y & s3);
+    // two-level select on the letter's bits (Y and "any" have bit 0, Z and
+    // "any" bit 1): three conditional moves per dword
+    const bool b0 = (letter & 1u) != 0u, b1 = (letter & 2u) != 0u;
+    const uint64_t lo = b1 ? (b0 ? ma.x : mz.x) : (b0 ? my.x : mx.x);
+    const uint64_t hi = b1 ? (b0 ? ma.y : mz.y) : (b0 ? my.y : mx.y);
     return scale * static_cast<float>(__popcll(lo & q.x) + __popcll(hi & q.y));
 }
 
@@ -185,7 +197,7 @@ __global__ __launch_bounds__(kScThreads) void k_scorer_forward(ScorerFwdArgs A) 
                 for (int q = 0; q < 4; ++q) {
                     const int k = m * 16 + kq + q;
                     zz[q] = c[q] + L.b2[k];
-                    y += bf2f(f2bf(gelu(zz[q]))) * L.W3[k];
+                    y = fmaf(bf2f(f2bf(gelu(zz[q]))), L.W3[k], y);
                 }
                 if (A.z2_out && live)
                     *reinterpret_cast<float4*>(A.z2_out + i * kScH + m * 16 + kq) =
