@@ -301,13 +301,19 @@ __global__ __launch_bounds__(kThreads) void k_gen_reduce(GenArgs A) {
         }
         __syncthreads();
     }
+    // the waves' maxima combined in LDS, one device atomic per lane and
+    // workgroup (all workgroups leave together; atomics on one word queue)
+    __shared__ unsigned long long sWmax[LP];
+    if (tid < LP) sWmax[tid] = 0ull;
+    __syncthreads();
 #pragma unroll
     for (int a = 0; a < LP; ++a) {
         const double mx = wave_max_d(vmax[a]);
-        if (lane_id() == 0 && mx > 0.0)
-            atomicMax(reinterpret_cast<unsigned long long*>(&ctrl->maxbits[A.mx_out][a]),
-                      static_cast<unsigned long long>(d_to_bits(mx)));
+        if (lane_id() == 0 && mx > 0.0) atomicMax(&sWmax[a], static_cast<unsigned long long>(d_to_bits(mx)));
     }
+    __syncthreads();
+    if (tid < LP && sWmax[tid] != 0ull)
+        atomicMax(reinterpret_cast<unsigned long long*>(&ctrl->maxbits[A.mx_out][tid]), sWmax[tid]);
     if (finish_launch(ctrl)) {
         if (ntiles == 0 && __hip_atomic_load(&ctrl->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u) {
             ctrl->nf[A.out_buf] = 0;
