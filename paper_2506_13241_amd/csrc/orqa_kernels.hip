@@ -405,6 +405,7 @@ __device__ __forceinline__ CT rx_value(const GateTrig& g, int a, uint32_t kind, 
 }
 
 constexpr uint32_t kNoTile = 0xFFFFFFFFu;
+constexpr int kRxBatch = 2;  // 16-byte chunks per thread whose loads a wide-row loop issues together
 
 // One RX gate, software-pipelined over the tiles a workgroup takes: a tile is
 // loaded and planned (x-groups, merged order, emission plan, output counts),
@@ -530,18 +531,32 @@ __device__ __forceinline__ void rx_merge_body(const RxArgs& A, const GateTrig& g
                 }
                 if constexpr (!kStageC) {
                     if (filt) {  // a row is alive when some lane is above its threshold: chunks, then OR
-                        const uint32_t nc = (m * kCPR + kThreads - 1) / kThreads * kThreads;
-                        for (uint32_t c = tid; c < nc; c += kThreads) {
-                            const uint32_t e = c / kCPR, q = c % kCPR;
-                            int keep = 0;
-                            if (e < m) {
-                                const CT* src = Cin + rx_phys(T, e, nf, cap) * LP + q * kVPC;
+                        // kRxBatch chunks per thread at a time (loads in flight together)
+                        const uint32_t nc = (m * kCPR + kThreads * kRxBatch - 1) / (kThreads * kRxBatch) *
+                                            (kThreads * kRxBatch);
+                        for (uint32_t c0 = tid; c0 < nc; c0 += kThreads * kRxBatch) {
+                            CT va[kRxBatch][kVPC];
 #pragma unroll
-                                for (int j = 0; j < kVPC; ++j) keep |= absd(src[j]) > sThr[q * kVPC + j];
+                            for (int u = 0; u < kRxBatch; ++u) {
+                                const uint32_t c = c0 + uint32_t(u) * kThreads, e = c / kCPR, q = c % kCPR;
+                                if (e < m) {
+                                    const CT* src = Cin + rx_phys(T, e, nf, cap) * LP + q * kVPC;
+#pragma unroll
+                                    for (int j = 0; j < kVPC; ++j) va[u][j] = src[j];
+                                }
                             }
 #pragma unroll
-                            for (int o = 1; o < kCPR; o <<= 1) keep |= __shfl_xor(keep, o, 64);
-                            if (e < m && q == 0) sAlive[e] = uint8_t(keep);
+                            for (int u = 0; u < kRxBatch; ++u) {
+                                const uint32_t c = c0 + uint32_t(u) * kThreads, e = c / kCPR, q = c % kCPR;
+                                int keep = 0;
+                                if (e < m) {
+#pragma unroll
+                                    for (int j = 0; j < kVPC; ++j) keep |= absd(va[u][j]) > sThr[q * kVPC + j];
+                                }
+#pragma unroll
+                                for (int o = 1; o < kCPR; o <<= 1) keep |= __shfl_xor(keep, o, 64);
+                                if (e < m && q == 0) sAlive[e] = uint8_t(keep);
+                            }
                         }
                     }
                 }
@@ -796,21 +811,44 @@ __device__ __forceinline__ void rx_merge_body(const RxArgs& A, const GateTrig& g
                     }
                 }
                 if constexpr (!kStageC) {  // coefficients in 16-byte chunks, one thread per chunk
-                    for (uint32_t c = tid; c < tot * kCPR; c += kThreads) {
-                        const uint32_t i = c / kCPR, q = c % kCPR;
-                        const uint32_t en = sOut[side][i];
-                        const uint32_t e = en & 0x3FFu, e2 = (en >> 10) & 0x3FFu, kind = en >> 20;
-                        const uint64_t o = base + i;
-                        if (o >= cap) continue;
-                        const uint64_t po = side ? cap - 1 - o : o;
-                        const CT* ce = Cin + rx_phys(T, e, nf, cap) * LP + q * kVPC;
-                        const CT* ce2 = Cin + rx_phys(T, kind == 3 ? e2 : e, nf, cap) * LP + q * kVPC;
-                        CT* dst = Cout + po * LP + q * kVPC;
+                    // kRxBatch chunks per thread at a time: their loads are all in
+                    // flight before the first store (one latency per batch)
+                    for (uint32_t c0 = tid; c0 < tot * kCPR; c0 += kThreads * kRxBatch) {
+                        CT va[kRxBatch][kVPC], vb[kRxBatch][kVPC];
+                        uint32_t wk[kRxBatch];  // kind, or 4: nothing to write
+                        uint64_t wpo[kRxBatch];
 #pragma unroll
-                        for (int j = 0; j < kVPC; ++j) {
-                            const CT v = rx_value<CT, LP>(g, int(q) * kVPC + j, kind, side == 0, ce[j], ce2[j]);
-                            dst[j] = v;
-                            vmax[j] = fmax(vmax[j], absd(v));
+                        for (int u = 0; u < kRxBatch; ++u) {
+                            const uint32_t c = c0 + uint32_t(u) * kThreads;
+                            wk[u] = 4u;
+                            wpo[u] = 0;
+                            if (c >= tot * kCPR) continue;
+                            const uint32_t i = c / kCPR, q = c % kCPR;
+                            const uint32_t en = sOut[side][i];
+                            const uint32_t e = en & 0x3FFu, e2 = (en >> 10) & 0x3FFu, kind = en >> 20;
+                            const uint64_t o = base + i;
+                            if (o >= cap) continue;
+                            const CT* ce = Cin + rx_phys(T, e, nf, cap) * LP + q * kVPC;
+                            const CT* ce2 = Cin + rx_phys(T, kind == 3 ? e2 : e, nf, cap) * LP + q * kVPC;
+#pragma unroll
+                            for (int j = 0; j < kVPC; ++j) {
+                                va[u][j] = ce[j];
+                                vb[u][j] = ce2[j];
+                            }
+                            wk[u] = kind;
+                            wpo[u] = (side ? cap - 1 - o : o) * LP + q * kVPC;
+                        }
+#pragma unroll
+                        for (int u = 0; u < kRxBatch; ++u) {
+                            if (wk[u] == 4u) continue;
+                            const uint32_t q = (c0 + uint32_t(u) * kThreads) % kCPR;
+                            CT* dst = Cout + wpo[u];
+#pragma unroll
+                            for (int j = 0; j < kVPC; ++j) {
+                                const CT v = rx_value<CT, LP>(g, int(q) * kVPC + j, wk[u], side == 0, va[u][j], vb[u][j]);
+                                dst[j] = v;
+                                vmax[j] = fmax(vmax[j], absd(v));
+                            }
                         }
                     }
                 }
@@ -869,7 +907,7 @@ __global__ __launch_bounds__(kThreads, 4) void k_rx_merge(RxArgs A, GateTrig g) 
 
 // Wider rows: every tile written as soon as its offsets are known.
 template <typename CT, int LP>
-__global__ __launch_bounds__(kThreads) void k_rx_merge_wide(RxArgs A, GateTrig g) {
+__global__ __launch_bounds__(kThreads, 4) void k_rx_merge_wide(RxArgs A, GateTrig g) {
     rx_merge_body<CT, LP, 0>(A, g);
 }
 
