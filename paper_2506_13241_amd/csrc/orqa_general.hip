@@ -115,9 +115,7 @@ __global__ __launch_bounds__(kThreads) void k_gen_branch(GenArgs A, GateTrig g) 
         uint32_t tot, off[kGenIPT];
         scan_striped4(nout, sWave, off, tot);
         if (wave == 0) {
-            const uint64_t gmax = A.max_tiles / 64 + 2;
             const uint64_t b = lookback_wave2(A.status, A.status + 2 * A.max_tiles, tile, ep, tot, &ctrl->err);
-            (void)gmax;
             if (lane_id() == 0) sBase = b;
         }
         __syncthreads();
