@@ -1,14 +1,14 @@
 """What the trained scorer gains over plain magnitude truncation, and its
 fallback to magnitude truncation (needs a GPU).
 
-127-qubit kicked Ising, theta_h = 0.8, observable Z62.  The gain is judged
-by a magnitude run at eps0 = 2.5e-6, a quarter of the smallest threshold
+127-qubit kicked Ising, theta_h = 0.8, observable Z62.  The gain is measured
+against a reference magnitude run at eps0 = 2.5e-6, a quarter of the smallest threshold
 compared and independent of both arms, over the 6 Trotter steps that run
 fits on one GPU.  The committed network (paper_2506_13241_amd/data, trained
 by paper_2506_13241_amd.train_scorer on strings from 8-step runs,
 horizon-3 labels) at eps0 = 5e-6 must keep fewer strings summed over the
 steps than magnitude truncation at 1e-5, with a smaller worst |<Z62> -
-judge|, both below 1e-3 (the gain at matched error)."""
+reference|, both below 1e-3 (the gain at matched error)."""
 
 import os
 import sys
@@ -55,11 +55,11 @@ def _setup():
 
 def test_learned_truncation_keeps_fewer_strings_at_lower_error():
     P, run = _setup()
-    judge, n_j, _ = run(2.5e-6, P.PS_TRUNC_MAGNITUDE, 6)
-    say(f"judge eps 2.5e-6: sum|O| = {n_j:.3e}")
+    ref, n_j, _ = run(2.5e-6, P.PS_TRUNC_MAGNITUDE, 6)
+    say(f"reference eps 2.5e-6: sum|O| = {n_j:.3e}")
     ez_m, n_m, _ = run(1e-5, P.PS_TRUNC_MAGNITUDE, 6)
     ez_l, n_l, _ = run(5e-6, P.PS_TRUNC_LEARNED, 6)
-    em, el = np.abs(ez_m - judge), np.abs(ez_l - judge)
+    em, el = np.abs(ez_m - ref), np.abs(ez_l - ref)
     say(f"magnitude 1e-5: sum|O| {n_m:.3e} max {em.max():.2e} | learned 5e-6: sum|O| {n_l:.3e} max {el.max():.2e}")
     assert n_l < 0.5 * n_m
     assert el.max() < em.max() <= 1e-3
